@@ -1,0 +1,286 @@
+/*
+ * md.h - C ABI of libmdx, an MI355X (gfx950) molecular-dynamics hot path:
+ * Lennard-Jones / Kob-Andersen pair forces over Verlet neighbour lists built
+ * from a particle sort by cell, and velocity-Verlet integration with the
+ * position and velocity updates in double-single (FP32-pair) arithmetic.
+ *
+ * The method is that of Colberg & Hoefling, "Highly accelerated simulations
+ * of glassy dynamics using GPUs: caveats on limited floating-point precision"
+ * (arXiv:0912.3824):
+ *   - Sec. 2.2 (the MD integration step): velocity Verlet, Verlet lists with
+ *     a skin, cell binning by a sort on the 1-D cell index, rebuild when the
+ *     maximum displacement since the last build demands it;
+ *   - Sec. 2.4 and Alg. 1 (double-single arithmetic): the velocity-Verlet
+ *     update and the force summation in double-single, the pair force itself
+ *     in single precision;
+ *   - Sec. 3: LJ 12-6 potential cut off at rc = 2.5 sigma, dt* = 0.001;
+ *   - Sec. 5: the Kob-Andersen pair table (eps_AB = 1.5, eps_BB = 0.5,
+ *     sigma_AB = 0.8, sigma_BB = 0.88, equal masses).
+ *
+ * Conventions shared by every entry point
+ *   - Units are reduced LJ units (sigma_AA, eps_AA, m).  Boxes are cubic and
+ *     periodic.  Energies are shifted to vanish at the cutoff, forces are not.
+ *   - A system is a pool of `max_slots` replica slots over one particle arena;
+ *     a single system is a pool with one attached replica.  Replicas are
+ *     independent: the trajectory of a replica does not depend on which other
+ *     replicas share the pool (bitwise).
+ *   - Memory: the CALLER owns all device memory.  It passes one device
+ *     workspace of md_workspace_bytes() bytes and a hipStream_t (as void*);
+ *     the library never allocates or frees device memory.  The library owns
+ *     only the host handle (freed by md_destroy) and its host-side mirrors.
+ *   - Host arrays passed in are read before the call returns; host arrays
+ *     passed out are written before the call returns.
+ *   - Asynchrony: calls that only launch work (md_step, md_advance,
+ *     md_rebuild_neighbours, md_forces with NULL outputs) return before the
+ *     GPU finishes.  Calls that return data to the host synchronise the stream.
+ *   - Errors: no exception crosses the ABI.  Every call returns an md_status;
+ *     md_last_error() holds a human-readable description of the last failure
+ *     on that handle.  Device-side failures (list overflow, non-finite
+ *     coordinates) set sticky per-replica status bits that md_poll() and
+ *     md_observables() report and that turn later calls into MD_E_CAPACITY or
+ *     MD_E_NONFINITE for that replica.
+ *   - Threading: one handle must not be used from two host threads at once.
+ */
+#ifndef MDX_MD_H
+#define MDX_MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MD_ABI_VERSION 1
+
+typedef struct md_system md_system;
+
+typedef enum {
+    MD_OK = 0,
+    MD_E_ARG = -1,       /* invalid argument or configuration */
+    MD_E_BOX = -2,       /* box shorter than twice the largest list radius */
+    MD_E_WORKSPACE = -3, /* workspace missing, misaligned or too small */
+    MD_E_CAPACITY = -4,  /* particle/cell arena full or neighbour list overflow */
+    MD_E_NONFINITE = -5, /* a coordinate or force became NaN/Inf */
+    MD_E_HIP = -6,       /* a HIP runtime call failed */
+    MD_E_NOSLOT = -7,    /* slot index out of range, busy or empty */
+    MD_E_STATE = -8      /* call not valid in the current state */
+} md_status;
+
+/* Arithmetic of the path (Sec. 2.4 defines the double-single split). */
+typedef enum {
+    MD_FP32 = 0,    /* FP32 pair force, FP32 force sum, FP32 velocity Verlet */
+    MD_DS = 1,      /* FP32 pair force, double-single force sum (error-free
+                       transformations), double-single velocity Verlet (Alg. 1) */
+    MD_MIXED64 = 2, /* FP32 pair force, FP64 force sum, FP64 velocity Verlet */
+    MD_FP64 = 3     /* everything in FP64 */
+} md_precision;
+
+/* Per-replica status bits (sticky until md_detach / md_restore). */
+#define MD_ST_LIST_OVERFLOW 1 /* a particle had more neighbours than nbr_capacity */
+#define MD_ST_NONFINITE 2     /* a position became NaN/Inf */
+#define MD_ST_LOST 4          /* cell counting lost particles (follows NONFINITE) */
+#define MD_ST_AT_FULL_STEP 256 /* not an error: velocities are at a full step
+                                  (reported by md_poll only) */
+
+/*
+ * Pool configuration.  Pair parameters are a symmetric 2x2 table indexed
+ * [a*2+b] for species a, b in {0 (A), 1 (B)}; with n_species == 1 only [0]
+ * is used.  rcut holds absolute cutoffs (the KA reading is 2.5 sigma_ab).
+ * The list radius of a pair is rcut[ab] + skin (Sec. 2.2).
+ */
+typedef struct {
+    int32_t n_species;     /* 1 or 2 */
+    int32_t precision;     /* md_precision */
+    double eps[4];
+    double sigma[4];
+    double rcut[4];
+    double mass;           /* equal masses (Sec. 5); > 0 */
+    double dt;             /* time step; > 0 */
+    double skin;           /* Verlet skin; > 0 */
+    int32_t nbr_capacity;  /* list entries per particle; 0 = derive from max_density */
+    int32_t max_slots;     /* replicas attachable at once; >= 1 */
+    int64_t max_particles; /* particle arena capacity; >= 1 */
+    int64_t max_cells;     /* cell arena capacity; 0 = derive from max_particles */
+    double max_density;    /* density used to derive capacities; 0 = 1.2 */
+} md_config;
+
+/* One replica: N particles in a cubic box of edge `box`. */
+typedef struct {
+    int32_t n;
+    int32_t reserved;
+    double box;
+} md_replica;
+
+/* Observables of one replica at its current (full) step, FP64 sums over the
+ * per-particle values in a fixed order. */
+typedef struct {
+    double epot;        /* sum_i e_i, e_i = 1/2 sum_j V_ts(r_ij) */
+    double ekin;        /* 1/2 m sum_i v_i^2 */
+    double etot;
+    double temperature; /* 2 E_kin / (3 N) */
+    double virial;      /* W = sum_{i<j} r_ij . F_ij */
+    double pressure;    /* (2 E_kin + W) / (3 V) */
+    double momentum[3]; /* m sum_i v_i */
+    int64_t step;       /* steps completed since attach */
+    int64_t n_rebuilds; /* neighbour-list builds since attach (incl. the first) */
+    int32_t status;     /* MD_ST_* bits */
+    int32_t n;          /* particles (0 if the slot is empty) */
+} md_obs;
+
+/* Launch shapes (the autotuner's knobs).  None changes any result bit. */
+typedef struct {
+    int32_t step_block;    /* threads per block of the fused step kernel: 64..1024, multiple of 64 */
+    int32_t build_width;   /* cells per row segment staged in LDS by the list build: 1..16 */
+    int32_t build_block;   /* threads per block of the list build: 64..1024, multiple of 64 */
+    int32_t graph_steps;   /* steps per captured hipGraph (even, 2..256); 0 = no graphs */
+    int32_t xcd_remap;     /* 1 = map consecutive particle tiles to one XCD (8 XCDs) */
+    int32_t reserved[3];
+} md_launch;
+
+/* ---- sizing and lifetime ------------------------------------------------ */
+
+/* Bytes of device workspace a pool with this configuration needs (>= 0), or
+ * a negative md_status if the configuration is invalid.  Host only; no GPU
+ * call. */
+int64_t md_workspace_bytes(const md_config *cfg);
+
+/* Validate a configuration and a replica against it without touching the
+ * GPU: returns MD_OK, MD_E_ARG or MD_E_BOX.  `rep` may be NULL. */
+md_status md_validate(const md_config *cfg, const md_replica *rep);
+
+/* Create an empty pool over the caller's workspace (device pointer,
+ * 256-byte aligned, ws_bytes >= md_workspace_bytes(cfg)) and stream
+ * (hipStream_t as void*, must not be the legacy NULL stream when graphs are
+ * used).  Clears the control words on the stream.  On success *out owns a
+ * host handle. */
+md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes,
+                    void *hip_stream, md_system **out);
+
+/* md_init (the one-call form): md_create, then md_attach of replicas
+ * 0..n_rep-1 into slots 0..n_rep-1.  species/pos/vel are host arrays of the
+ * concatenated replicas (sum of n entries; pos and vel [n][3] FP64). */
+md_status md_init(const md_config *cfg, const md_replica *reps, int32_t n_rep,
+                  const int32_t *species, const double *pos, const double *vel,
+                  void *workspace, int64_t ws_bytes, void *hip_stream,
+                  md_system **out);
+
+/* Free the host handle.  Device memory stays with the caller.  Safe on NULL. */
+void md_destroy(md_system *sys);
+
+/* ---- replicas (serving pool) --------------------------------------------- */
+
+/* Attach a replica to an empty slot: host FP64 positions (any image; they
+ * are wrapped into [0, box)), velocities and species (0/1) are converted to
+ * the pool's precision (double-single: hi = fl32(x), lo = fl32(x - hi)),
+ * sorted by cell on the host, uploaded, and the replica's first neighbour
+ * list is built.  The replica starts at step 0 with full-step velocities.
+ * Synchronises the stream.  Errors: MD_E_NOSLOT, MD_E_BOX, MD_E_CAPACITY
+ * (arena full or list overflow), MD_E_ARG. */
+md_status md_attach(md_system *sys, int32_t slot, const md_replica *rep,
+                    const int32_t *species, const double *pos, const double *vel);
+
+/* Release a slot and its arena ranges.  Pending work on the stream that
+ * still advances the replica must have finished (call md_poll first). */
+md_status md_detach(md_system *sys, int32_t slot);
+
+/* ---- the MD step ---------------------------------------------------------- */
+
+/* Rebuild (re-sort by cell, then Verlet lists) every attached replica now,
+ * at its current positions (Sec. 2.2).  Asynchronous. */
+md_status md_rebuild_neighbours(md_system *sys);
+
+/* Evaluate forces, per-particle energies and virials at the current
+ * positions of every attached replica (no state change).  If f_host (n x 3)
+ * or e_host (n) are non-NULL, synchronises and copies the values of `slot`
+ * in particle-id order (input order of md_attach).  Asynchronous when both
+ * are NULL (slot is then ignored). */
+md_status md_forces(md_system *sys, int32_t slot, double *f_host, double *e_host);
+
+/* Advance every attached replica by n_steps velocity-Verlet steps (Sec. 2.2):
+ * per step one fused launch (force, second half-kick, first half-kick of the
+ * next step, drift, displacement check) plus the rebuild kernels, which do
+ * work only for replicas whose maximum displacement since their last build
+ * exceeds skin/2.  Replays captured hipGraphs where possible.  Replicas end
+ * at full-step velocities.  Asynchronous. */
+md_status md_step(md_system *sys, int64_t n_steps);
+
+/* Serving form: set the absolute step at which a replica stops
+ * (>= its current step).  Takes effect for launches issued afterwards. */
+md_status md_set_target(md_system *sys, int32_t slot, int64_t target_step);
+
+/* Serving form: issue n_launch step launches for the whole pool; each
+ * replica advances until it reaches its target, then finalises (full-step
+ * velocities) and idles.  Asynchronous. */
+md_status md_advance(md_system *sys, int64_t n_launch);
+
+/* Synchronise and read every slot's completed step count (steps[max_slots],
+ * -1 for empty slots) and status bits (status[max_slots]); either may be
+ * NULL.  Returns MD_OK even if replicas have error bits set. */
+md_status md_poll(md_system *sys, int64_t *steps, int32_t *status);
+
+/* Synchronise and compute the observables of every slot (out[max_slots]).
+ * Replicas must be at full steps (true after md_step, or once md_advance
+ * reached their target). */
+md_status md_observables(md_system *sys, md_obs *out);
+
+/* Multiply the velocities of a replica by `factor` (velocity rescaling for
+ * host-driven equilibration).  Asynchronous. */
+md_status md_scale_velocities(md_system *sys, int32_t slot, double factor);
+
+/* Block until all work on the pool's stream has finished. */
+md_status md_sync(md_system *sys);
+
+/* ---- state access ---------------------------------------------------------- */
+
+/* Copy a replica's state to the host in particle-id order: positions folded
+ * into [0, box) (FP64; double-single as hi + lo), velocities, and the image
+ * counters such that pos + image * box is the unwrapped trajectory.  Any
+ * pointer may be NULL.  Synchronises. */
+md_status md_get_state(md_system *sys, int32_t slot, double *pos, double *vel,
+                       int32_t *image);
+
+/* Size in bytes of a bit-exact checkpoint of a slot (> 0), or < 0 on error. */
+int64_t md_checkpoint_bytes(md_system *sys, int32_t slot);
+
+/* Write a bit-exact checkpoint of a slot (state words incl. double-single lo
+ * words, particle order, list reference positions, image counters, step and
+ * phase) into a host buffer of md_checkpoint_bytes() bytes.  Synchronises. */
+md_status md_save(md_system *sys, int32_t slot, void *blob, int64_t bytes);
+
+/* Attach a checkpoint to an empty slot of a pool with the same precision,
+ * pair table, dt and skin.  The continued trajectory is bitwise identical to
+ * the uninterrupted one.  Synchronises. */
+md_status md_restore(md_system *sys, int32_t slot, const void *blob, int64_t bytes);
+
+/* Neighbour lists of a replica in particle-id order (tests): counts[n] and
+ * ids[n][cap] (unused entries -1).  Synchronises. */
+md_status md_debug_neighbours(md_system *sys, int32_t slot, int32_t *counts,
+                              int32_t *ids, int32_t cap);
+
+/* ---- launch shapes ----------------------------------------------------------- */
+
+md_status md_get_launch(const md_system *sys, md_launch *out);
+/* Changes take effect for later launches; captured graphs are dropped. */
+md_status md_set_launch(md_system *sys, const md_launch *in);
+
+/* ---- double-single arithmetic self-test (Sec. 2.4, Alg. 1) -------------------- */
+
+/* Element-wise double-single operation on device arrays of n (hi, lo) float
+ * pairs, on the given stream: op 0 = add (Alg. 1), 1 = subtract,
+ * 2 = multiply (exact FMA product of the high words plus cross terms),
+ * 3 = compensated sum of a[k].hi over k (out[0] only; Sum2-style error-free
+ * accumulation as used for the force sum).  Asynchronous. */
+md_status md_ds_eval(int32_t op, int64_t n, const float *a, const float *b, float *out,
+                     void *hip_stream);
+
+/* ---- errors --------------------------------------------------------------------- */
+
+const char *md_strerror(md_status st);
+/* Last error text of a handle ("" if none); valid until the next call. */
+const char *md_last_error(const md_system *sys);
+int32_t md_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDX_MD_H */

@@ -1,0 +1,1074 @@
+// HIP kernels of libmdx for gfx950 (wave64).
+//
+// One MD step (Sec. 2.2, velocity Verlet with Verlet lists) is one fused
+// launch of k_step plus three rebuild kernels that exit at once unless the
+// replica's maximum displacement since its last list build exceeded skin/2:
+//
+//   k_step<P>    per particle: force over its Verlet list (FP32 pair term,
+//                sum in the precision P), second half-kick of step n (full-
+//                step velocity), first half-kick of step n+1, drift,
+//                fixed-point snapshot of the new position, displacement test
+//                against the list's reference position, and the count of the
+//                particle's new cell (for the sort, Sec. 2.2 cell binning).
+//   k_scan       per replica: exclusive scan of the cell counts -> cell starts.
+//   k_permute<P> per cell (one wave): stable counting-sort scatter.  Members
+//                of a new cell come from the 27 surrounding old cells (a
+//                particle moves less than one cell between builds); a ballot
+//                over them in old slot order gives each its new slot.  The
+//                whole particle record is gathered into the scratch arena,
+//                positions folded back into the box.
+//   k_build<P>   per row segment of cells (one workgroup): the segment's
+//                27-cell neighbourhood is staged in LDS, every member scans
+//                its own cell and then the 13 opposite cell pairs (Sec. 4.1)
+//                and writes its list column-major; the sorted record is
+//                copied back from scratch.
+//
+// Bitwise determinism: lists are in a canonical order (own cell, then +o/-o
+// pairs, slot order inside a cell), the sort is stable, each particle sums
+// its own list sequentially, and no floating-point atomics are used.  The
+// result for a replica therefore does not depend on launch shapes or on
+// other replicas in the pool.
+#include "md_dev.hpp"
+#include "kernels.hpp"
+
+// --------------------------------------------------------------- utilities
+__device__ __forceinline__ int remap_block(int b, int nblk, int on)
+{
+    // Consecutive tiles to one XCD: workgroups are dealt round-robin over
+    // the 8 XCDs, so block b runs on XCD b % 8.
+    if (!on) return b;
+    int per = nblk >> 3;
+    if (b < (per << 3)) return (b & 7) * per + (b >> 3);
+    return b;
+}
+
+__device__ __forceinline__ int slot_of_meta(uint32_t w) { return (int)(w >> SLOT_SHIFT); }
+
+__device__ __forceinline__ int find_item_slot(const int *pref, int nslots, int item)
+{
+    // pref[0..nslots] non-decreasing; find s with pref[s] <= item < pref[s+1]
+    int lo = 0, hi = nslots;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pref[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *need, const Ctl *ctl)
+{
+    if (force_slot == -1) return need[s] != 0;
+    if (force_slot == -2) return ctl[s].z != 0;
+    return s == force_slot;
+}
+
+__device__ __forceinline__ uint4 dbl2_to_u4(double a, double b)
+{
+    uint4 u;
+    unsigned long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    u.x = (uint32_t)x; u.y = (uint32_t)(x >> 32); u.z = (uint32_t)y; u.w = (uint32_t)(y >> 32);
+    return u;
+}
+__device__ __forceinline__ void u4_to_dbl2(uint4 u, double &a, double &b)
+{
+    a = __longlong_as_double(((unsigned long long)u.y << 32) | u.x);
+    b = __longlong_as_double(((unsigned long long)u.w << 32) | u.z);
+}
+
+// ------------------------------------------------------- per-precision state
+template <int P> struct State;
+
+template <> struct State<PREC_FP32> {
+    float x, y, z, vx, vy, vz;
+    __device__ void load(const KArena &A, int i)
+    {
+        float4 a = ((const float4 *)A.st[0])[i], b = ((const float4 *)A.st[1])[i];
+        x = a.x; y = a.y; z = a.z; vx = b.x; vy = b.y; vz = b.z;
+    }
+    __device__ void store(const KArena &A, int i) const
+    {
+        ((float4 *)A.st[0])[i] = make_float4(x, y, z, 0.0f);
+        ((float4 *)A.st[1])[i] = make_float4(vx, vy, vz, 0.0f);
+    }
+};
+
+template <> struct State<PREC_DS> {
+    dsf x, y, z, vx, vy, vz;
+    __device__ void load(const KArena &A, int i)
+    {
+        float4 a = ((const float4 *)A.st[0])[i], b = ((const float4 *)A.st[1])[i],
+               c = ((const float4 *)A.st[2])[i];
+        x = {a.x, a.w}; y = {a.y, b.x}; z = {a.z, b.y};
+        vx = {b.z, c.y}; vy = {b.w, c.z}; vz = {c.x, c.w};
+    }
+    __device__ void store(const KArena &A, int i) const
+    {
+        ((float4 *)A.st[0])[i] = make_float4(x.hi, y.hi, z.hi, x.lo);
+        ((float4 *)A.st[1])[i] = make_float4(y.lo, z.lo, vx.hi, vy.hi);
+        ((float4 *)A.st[2])[i] = make_float4(vz.hi, vx.lo, vy.lo, vz.lo);
+    }
+};
+
+struct StateD {
+    double x, y, z, vx, vy, vz;
+    __device__ void load(const KArena &A, int i)
+    {
+        double2 a = ((const double2 *)A.st[0])[i], b = ((const double2 *)A.st[1])[i],
+                c = ((const double2 *)A.st[2])[i];
+        x = a.x; y = a.y; z = b.x; vx = b.y; vy = c.x; vz = c.y;
+    }
+    __device__ void store(const KArena &A, int i) const
+    {
+        ((double2 *)A.st[0])[i] = make_double2(x, y);
+        ((double2 *)A.st[1])[i] = make_double2(z, vx);
+        ((double2 *)A.st[2])[i] = make_double2(vy, vz);
+    }
+};
+template <> struct State<PREC_MIX> : StateD {};
+template <> struct State<PREC_FP64> : StateD {};
+
+// ---------------------------------------------------- force accumulators
+template <int P> struct FAcc;
+
+template <> struct FAcc<PREC_FP32> {
+    float x, y, z;
+    __device__ void init() { x = y = z = 0.0f; }
+    __device__ void add(float fs, float dx, float dy, float dz, int, int, int)
+    {
+        x = __builtin_fmaf(fs, dx, x);
+        y = __builtin_fmaf(fs, dy, y);
+        z = __builtin_fmaf(fs, dz, z);
+    }
+    __device__ void get(double &fx, double &fy, double &fz) const { fx = x; fy = y; fz = z; }
+};
+
+template <> struct FAcc<PREC_DS> {
+    sum2f x, y, z;
+    __device__ void init() { x.init(); y.init(); z.init(); }
+    __device__ void add(float fs, float dx, float dy, float dz, int, int, int)
+    {
+        x.add(fs * dx);
+        y.add(fs * dy);
+        z.add(fs * dz);
+    }
+    __device__ void get(double &fx, double &fy, double &fz) const
+    {
+        fx = ds_to_double(x.result()); fy = ds_to_double(y.result()); fz = ds_to_double(z.result());
+    }
+};
+
+template <> struct FAcc<PREC_MIX> {
+    double x, y, z;
+    __device__ void init() { x = y = z = 0.0; }
+    __device__ void add(float fs, float, float, float, int ix, int iy, int iz)
+    {
+        double f = (double)fs;
+        x = __builtin_fma(f, (double)ix, x);
+        y = __builtin_fma(f, (double)iy, y);
+        z = __builtin_fma(f, (double)iz, z);
+    }
+    __device__ void get(double &fx, double &fy, double &fz) const { fx = x; fy = y; fz = z; }
+};
+
+// ------------------------------------------------------------ integration
+// Velocity-Verlet pieces: kick v += (dt/2m) F, drift r += dt v.
+__device__ __forceinline__ void kick(State<PREC_FP32> &s, const FAcc<PREC_FP32> &f, const IntegDev &g)
+{
+    s.vx = __builtin_fmaf(g.hf, f.x, s.vx);
+    s.vy = __builtin_fmaf(g.hf, f.y, s.vy);
+    s.vz = __builtin_fmaf(g.hf, f.z, s.vz);
+}
+__device__ __forceinline__ void drift(State<PREC_FP32> &s, const IntegDev &g)
+{
+    s.x = __builtin_fmaf(g.dtf, s.vx, s.x);
+    s.y = __builtin_fmaf(g.dtf, s.vy, s.y);
+    s.z = __builtin_fmaf(g.dtf, s.vz, s.z);
+}
+
+struct DsForce { dsf x, y, z; };
+__device__ __forceinline__ void kick(State<PREC_DS> &s, const DsForce &f, const IntegDev &g)
+{
+    dsf h = {g.h_hi, g.h_lo};
+    s.vx = ds_add(s.vx, ds_mul(f.x, h));
+    s.vy = ds_add(s.vy, ds_mul(f.y, h));
+    s.vz = ds_add(s.vz, ds_mul(f.z, h));
+}
+__device__ __forceinline__ void drift(State<PREC_DS> &s, const IntegDev &g)
+{
+    dsf dt = {g.dt_hi, g.dt_lo};
+    s.x = ds_add(s.x, ds_mul(s.vx, dt));
+    s.y = ds_add(s.y, ds_mul(s.vy, dt));
+    s.z = ds_add(s.z, ds_mul(s.vz, dt));
+}
+
+__device__ __forceinline__ void kickd(StateD &s, double fx, double fy, double fz, const IntegDev &g)
+{
+    s.vx = __builtin_fma(g.h, fx, s.vx);
+    s.vy = __builtin_fma(g.h, fy, s.vy);
+    s.vz = __builtin_fma(g.h, fz, s.vz);
+}
+__device__ __forceinline__ void driftd(StateD &s, const IntegDev &g)
+{
+    s.x = __builtin_fma(g.dt, s.vx, s.x);
+    s.y = __builtin_fma(g.dt, s.vy, s.y);
+    s.z = __builtin_fma(g.dt, s.vz, s.z);
+}
+
+// Fixed-point snapshot of a state's position.
+__device__ __forceinline__ uint4 snap_of(const State<PREC_FP32> &s, const RepDev &r, uint32_t w)
+{
+    return make_uint4(to_fixed((double)s.x, r.fxs), to_fixed((double)s.y, r.fxs), to_fixed((double)s.z, r.fxs), w);
+}
+__device__ __forceinline__ uint4 snap_of(const State<PREC_DS> &s, const RepDev &r, uint32_t w)
+{
+    return make_uint4(to_fixed(ds_to_double(s.x), r.fxs), to_fixed(ds_to_double(s.y), r.fxs),
+                      to_fixed(ds_to_double(s.z), r.fxs), w);
+}
+__device__ __forceinline__ uint4 snap_of(const StateD &s, const RepDev &r, uint32_t w)
+{
+    return make_uint4(to_fixed(s.x, r.fxs), to_fixed(s.y, r.fxs), to_fixed(s.z, r.fxs), w);
+}
+
+// ------------------------------------------------ pair constants per lane
+// Scaled units: separations in fixed-point units u = L / 2^32.  With
+// r2s = r^2 / u^2 the pair term needs rc^2/u^2, sigma^2/u^2 and 24 eps / u.
+struct LaneConsts {
+    float rc2s[2], sig2s[2], e24s[2];
+};
+
+__device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, const RepDev &r)
+{
+    LaneConsts c;
+    double u = (double)r.sc;
+    double iu2 = 1.0 / (u * u);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        int t = si * 2 + b;
+        c.rc2s[b] = (float)(pp.rc2d[t] * iu2);
+        c.sig2s[b] = (float)(pp.sig2d[t] * iu2);
+        c.e24s[b] = (float)(pp.eps24d[t] / u);
+    }
+    return c;
+}
+
+// Force (and optionally energy/virial) on particle i from its list, fixed-
+// point snapshots, FP32 pair term.  Returns the accumulated force.
+template <int P, bool EN>
+__device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
+                                            uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
+                                            FAcc<P> &acc, double &e_sum, double &w_sum)
+{
+    const int *__restrict__ lp = A.nbr + i;
+    const int cnt = A.nbr_cnt[i];
+    const size_t P_ = (size_t)A.P;
+    acc.init();
+    for (int k = 0; k < cnt; ++k) {
+        int j = __builtin_nontemporal_load(lp + (size_t)k * P_);
+        uint4 xj = snap[j];
+        int ix = (int)(xi.x - xj.x), iy = (int)(xi.y - xj.y), iz = (int)(xi.z - xj.z);
+        float dx = (float)ix, dy = (float)iy, dz = (float)iz;
+        float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        bool b = (xj.w & SPECIES_MASK) != 0;
+        float rc2 = b ? c.rc2s[1] : c.rc2s[0];
+        float sig2 = b ? c.sig2s[1] : c.sig2s[0];
+        float e24 = b ? c.e24s[1] : c.e24s[0];
+        float ir2 = __builtin_amdgcn_rcpf(r2);
+        float s2 = sig2 * ir2;
+        float s6 = s2 * s2 * s2;
+        float t = __builtin_fmaf(2.0f, s6, -1.0f);
+        float fs = e24 * ir2 * s6 * t;
+        bool in = r2 < rc2;
+        fs = in ? fs : 0.0f;
+        acc.add(fs, dx, dy, dz, ix, iy, iz);
+        if (EN) {
+            int tt = si * 2 + (b ? 1 : 0);
+            if (in) {
+                e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
+                w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
+            }
+        }
+    }
+}
+
+// FP64 path: double snapshots, textbook minimum image, FP64 pair term.
+__device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restrict__ snap, int i,
+                                          double xi, double yi, double zi, int si, const RepDev &r,
+                                          const PairDev &pp, double &fx, double &fy, double &fz,
+                                          bool en, double &e_sum, double &w_sum)
+{
+    const int *__restrict__ lp = A.nbr + i;
+    const int cnt = A.nbr_cnt[i];
+    const size_t P_ = (size_t)A.P;
+    const uint4 *__restrict__ snap1 = snap + P_;
+    fx = fy = fz = 0.0;
+    double rc2[2], sig2[2], e24[2];
+    rc2[0] = pp.rc2d[si * 2]; rc2[1] = pp.rc2d[si * 2 + 1];
+    sig2[0] = pp.sig2d[si * 2]; sig2[1] = pp.sig2d[si * 2 + 1];
+    e24[0] = pp.eps24d[si * 2]; e24[1] = pp.eps24d[si * 2 + 1];
+    for (int k = 0; k < cnt; ++k) {
+        int j = __builtin_nontemporal_load(lp + (size_t)k * P_);
+        double xj, yj, zj, wj;
+        u4_to_dbl2(snap[j], xj, yj);
+        u4_to_dbl2(snap1[j], zj, wj);
+        double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+        dx -= r.L * rint(dx * r.invL);
+        dy -= r.L * rint(dy * r.invL);
+        dz -= r.L * rint(dz * r.invL);
+        double r2 = dx * dx + dy * dy + dz * dz;
+        int b = meta_of_bits(wj) & 1;
+        double ir2 = 1.0 / r2;
+        double s2 = sig2[b] * ir2;
+        double s6 = s2 * s2 * s2;
+        double ff = e24[b] * ir2 * s6 * (2.0 * s6 - 1.0);
+        bool in = r2 < rc2[b];
+        ff = in ? ff : 0.0;
+        fx += ff * dx;
+        fy += ff * dy;
+        fz += ff * dz;
+        if (en && in) {
+            int tt = si * 2 + b;
+            e_sum += 0.5 * (pp.eps4d[tt] * s6 * (s6 - 1.0) - pp.shiftd[tt]);
+            w_sum += 0.5 * ff * r2;
+        }
+    }
+}
+
+// ------------------------------------------------------------ k_step
+enum { M_ADV = 0, M_FIN = 1, M_IDLE = 2 };
+
+template <int P, bool OBS>
+__global__ void __launch_bounds__(1024) k_step(const StepArgs a)
+{
+    const KArena &A = a.A;
+    const int nblk = gridDim.x;
+    const int blk = remap_block(blockIdx.x, nblk, a.xcd);
+    const int i = blk * blockDim.x + threadIdx.x;
+    constexpr int NS = Traits<P>::NS;
+
+    if (!OBS) { // clear the other parity's cell counters (read by the last rebuild)
+        const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+        for (int c = gt; c < a.cell_cap; c += nblk * blockDim.x) a.count_other[c] = 0;
+    }
+    if (i >= A.P) return;
+
+    uint4 s0 = a.snap_cur[i];
+    uint4 s1;
+    uint32_t meta;
+    if (NS == 2) {
+        s1 = a.snap_cur[(size_t)A.P + i];
+        double zz, ww;
+        u4_to_dbl2(s1, zz, ww);
+        meta = meta_of_bits(ww);
+    } else {
+        meta = s0.w;
+    }
+    if (meta == NO_SLOT) return;
+    const int r = slot_of_meta(meta);
+    if (r >= a.max_slots) return;
+    const Ctl ctl = a.ctl_cur[r];
+    if (!ctl.z) return;
+    const RepDev rp = a.rep[r];
+    int mode;
+    if (OBS) {
+        mode = M_FIN;
+    } else {
+        const int tgt = a.target[r];
+        mode = ctl.x < tgt ? M_ADV : (ctl.y ? M_IDLE : M_FIN);
+        if (i == rp.off) { // the replica's first particle owns its control words
+            Ctl nx = ctl;
+            if (mode == M_ADV) { nx.x = ctl.x + 1; nx.y = 0; }
+            else nx.y = 1;
+            a.ctl_next[r] = nx;
+            a.need_other[r] = 0;
+        }
+        if (mode == M_IDLE) {
+            a.snap_next[i] = s0;
+            if (NS == 2) a.snap_next[(size_t)A.P + i] = s1;
+            return;
+        }
+    }
+    const int si = (int)(meta & SPECIES_MASK);
+    double e_sum = 0.0, w_sum = 0.0;
+    double fxd, fyd, fzd;
+
+    State<P> st;
+    st.load(A, i);
+
+    if constexpr (P == PREC_FP64) {
+        double xi, yi, zi, wi;
+        u4_to_dbl2(s0, xi, yi);
+        u4_to_dbl2(s1, zi, wi);
+        force_dbl(A, a.snap_cur, i, xi, yi, zi, si, rp, a.pp, fxd, fyd, fzd, OBS, e_sum, w_sum);
+        if (OBS) {
+            double *o = a.obs + (size_t)i * 8;
+            o[0] = fxd; o[1] = fyd; o[2] = fzd; o[3] = e_sum; o[4] = w_sum;
+            o[5] = st.vx; o[6] = st.vy; o[7] = st.vz;
+            return;
+        }
+        if (!ctl.y) kickd(st, fxd, fyd, fzd, a.ig);
+        if (mode == M_ADV) {
+            kickd(st, fxd, fyd, fzd, a.ig);
+            driftd(st, a.ig);
+        }
+    } else {
+        const LaneConsts c = lane_consts(a.pp, si, rp);
+        FAcc<P> acc;
+        force_fixed<P, OBS>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum);
+        if (OBS) {
+            acc.get(fxd, fyd, fzd);
+            double *o = a.obs + (size_t)i * 8;
+            o[0] = fxd; o[1] = fyd; o[2] = fzd; o[3] = e_sum; o[4] = w_sum;
+            double vx, vy, vz;
+            if constexpr (P == PREC_FP32) { vx = st.vx; vy = st.vy; vz = st.vz; }
+            else if constexpr (P == PREC_DS) { vx = ds_to_double(st.vx); vy = ds_to_double(st.vy); vz = ds_to_double(st.vz); }
+            else { vx = st.vx; vy = st.vy; vz = st.vz; }
+            o[5] = vx; o[6] = vy; o[7] = vz;
+            return;
+        }
+        if constexpr (P == PREC_FP32) {
+            if (!ctl.y) kick(st, acc, a.ig);
+            if (mode == M_ADV) { kick(st, acc, a.ig); drift(st, a.ig); }
+        } else if constexpr (P == PREC_DS) {
+            DsForce F = {acc.x.result(), acc.y.result(), acc.z.result()};
+            if (!ctl.y) kick(st, F, a.ig);
+            if (mode == M_ADV) { kick(st, F, a.ig); drift(st, a.ig); }
+        } else { // MIXED64: FP64 sum of FP32 pair terms
+            fxd = acc.x; fyd = acc.y; fzd = acc.z;
+            if (!ctl.y) kickd(st, fxd, fyd, fzd, a.ig);
+            if (mode == M_ADV) { kickd(st, fxd, fyd, fzd, a.ig); driftd(st, a.ig); }
+        }
+    }
+    st.store(A, i);
+    if (mode != M_ADV) { // finalised: positions unchanged
+        a.snap_next[i] = s0;
+        if (NS == 2) a.snap_next[(size_t)A.P + i] = s1;
+        return;
+    }
+
+    // new snapshot, displacement test, cell count
+    int cell;
+    bool far, bad;
+    if constexpr (P == PREC_FP64) {
+        double w = bits_of_meta(meta);
+        a.snap_next[i] = dbl2_to_u4(st.x, st.y);
+        a.snap_next[(size_t)A.P + i] = dbl2_to_u4(st.z, w);
+        double rx, ry, rz, rw;
+        u4_to_dbl2(A.xref[i], rx, ry);
+        u4_to_dbl2(A.xref[(size_t)A.P + i], rz, rw);
+        double dx = st.x - rx, dy = st.y - ry, dz = st.z - rz;
+        dx -= rp.L * rint(dx * rp.invL);
+        dy -= rp.L * rint(dy * rp.invL);
+        dz -= rp.L * rint(dz * rp.invL);
+        far = dx * dx + dy * dy + dz * dz > a.pp.hs2d;
+        bad = !isfinite(st.x + st.y + st.z);
+        cell = dbl_cell(st.x, st.y, st.z, rp.L, rp.invL, rp.nd);
+    } else {
+        uint4 X = snap_of(st, rp, meta);
+        a.snap_next[i] = X;
+        uint4 R = A.xref[i];
+        float dx = (float)(int)(X.x - R.x), dy = (float)(int)(X.y - R.y), dz = (float)(int)(X.z - R.z);
+        float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        float thr = (float)(a.pp.hs2d / ((double)rp.sc * (double)rp.sc));
+        far = d2 > thr;
+        if constexpr (P == PREC_FP32) bad = !isfinite(st.x + st.y + st.z);
+        else if constexpr (P == PREC_DS) bad = !isfinite(st.x.hi + st.y.hi + st.z.hi);
+        else bad = !isfinite(st.x + st.y + st.z);
+        cell = rp.nd == 1 ? 0 : fixed_cell(X.x, X.y, X.z, rp.nd);
+    }
+    atomicAdd(a.count_cur + rp.coff + cell, 1);
+    if (far) atomicOr(a.need_cur + r, 1);
+    if (bad) atomicOr(a.status + r, 2);
+}
+
+// ------------------------------------------------------------ k_count
+// Cell counts for a rebuild forced from the host (md_rebuild_neighbours).
+template <int P>
+__global__ void k_count(const CountArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.P) return;
+    constexpr int NS = Traits<P>::NS;
+    uint4 s0 = a.snap[i];
+    uint32_t meta;
+    double x = 0, y = 0, z = 0, w = 0;
+    if (NS == 2) {
+        u4_to_dbl2(s0, x, y);
+        u4_to_dbl2(a.snap[(size_t)a.P + i], z, w);
+        meta = meta_of_bits(w);
+    } else meta = s0.w;
+    if (meta == NO_SLOT) return;
+    int r = slot_of_meta(meta);
+    if (r >= a.max_slots) return;
+    if (!slot_selected(r, a.force_slot, nullptr, a.ctl)) return;
+    RepDev rp = a.rep[r];
+    int cell;
+    if (NS == 2) cell = dbl_cell(x, y, z, rp.L, rp.invL, rp.nd);
+    else cell = rp.nd == 1 ? 0 : fixed_cell(s0.x, s0.y, s0.z, rp.nd);
+    atomicAdd(a.count + rp.coff + cell, 1);
+}
+
+// ------------------------------------------------------------ k_scan
+// One workgroup (1024 threads) per slot: exclusive scan of cell counts.
+__global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
+{
+    const int s = blockIdx.x;
+    if (s >= a.max_slots) return;
+    if (!slot_selected(s, a.force_slot, a.need, a.ctl)) return;
+    const RepDev rp = a.rep[s];
+    const int ncell = rp.nd * rp.nd * rp.nd;
+    const int T = blockDim.x, t = threadIdx.x;
+    const int per = (ncell + T - 1) / T;
+    const int c0 = min(t * per, ncell), c1 = min(c0 + per, ncell);
+    const int *cnt = a.count + rp.coff;
+    int local = 0;
+    for (int c = c0; c < c1; ++c) local += cnt[c];
+    // block exclusive scan of `local`
+    __shared__ int wsum[16];
+    const int lane = t & 63, wv = t >> 6;
+    int incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int k = 0; k < (T + 63) / 64; ++k) { int v = wsum[k]; wsum[k] = acc; acc += v; }
+    }
+    __syncthreads();
+    int base = rp.off + wsum[wv] + incl - local;
+    int *out = a.cs_new + rp.coff;
+    for (int c = c0; c < c1; ++c) { out[c] = base; base += cnt[c]; }
+    if (c1 == ncell && c0 < c1) {
+        out[ncell] = base;
+        if (base != rp.off + rp.n) atomicOr(a.status + s, 4 | 2);
+    }
+    if (ncell == 0 && t == 0) out[0] = rp.off;
+    if (t == 0) a.nreb[s] += 1;
+}
+
+// ------------------------------------------------------------ k_permute
+// One wave per new cell: stable scatter of its members into scratch.
+template <int P>
+__device__ __forceinline__ void fold_and_copy(const PermArgs &a, const RepDev &rp, int q, int dst)
+{
+    constexpr int NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    int4 m = ((const int4 *)A.meta)[q];
+    int ix = 0, iy = 0, iz = 0;
+    if constexpr (P == PREC_FP32) {
+        float4 p = ((const float4 *)A.st[0])[q];
+        float *c[3] = {&p.x, &p.y, &p.z};
+        int *im[3] = {&ix, &iy, &iz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (*c[d] < 0.0f) { *c[d] += rp.Lf; *im[d] -= 1; }
+            if (*c[d] >= rp.Lf) { *c[d] -= rp.Lf; *im[d] += 1; }
+        }
+        ((float4 *)a.sc_st[0])[dst] = p;
+        a.sc_st[1][dst] = A.st[1][q];
+    } else if constexpr (P == PREC_DS) {
+        float4 w0 = ((const float4 *)A.st[0])[q], w1 = ((const float4 *)A.st[1])[q];
+        dsf x = {w0.x, w0.w}, y = {w0.y, w1.x}, z = {w0.z, w1.y};
+        dsf L = {rp.L_hi, rp.L_lo};
+        dsf *c[3] = {&x, &y, &z};
+        int *im[3] = {&ix, &iy, &iz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (c[d]->hi < 0.0f) { *c[d] = ds_add(*c[d], L); *im[d] -= 1; }
+            dsf t = ds_sub(*c[d], L);
+            if (t.hi >= 0.0f) { *c[d] = t; *im[d] += 1; }
+        }
+        ((float4 *)a.sc_st[0])[dst] = make_float4(x.hi, y.hi, z.hi, x.lo);
+        ((float4 *)a.sc_st[1])[dst] = make_float4(y.lo, z.lo, w1.z, w1.w);
+        a.sc_st[2][dst] = A.st[2][q];
+    } else {
+        double2 w0 = ((const double2 *)A.st[0])[q], w1 = ((const double2 *)A.st[1])[q];
+        double *c[3] = {&w0.x, &w0.y, &w1.x};
+        int *im[3] = {&ix, &iy, &iz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (*c[d] < 0.0) { *c[d] += rp.L; *im[d] -= 1; }
+            if (*c[d] >= rp.L) { *c[d] -= rp.L; *im[d] += 1; }
+        }
+        ((double2 *)a.sc_st[0])[dst] = w0;
+        ((double2 *)a.sc_st[1])[dst] = w1;
+        a.sc_st[2][dst] = A.st[2][q];
+    }
+    m.x += ix; m.y += iy; m.z += iz;
+    ((int4 *)a.sc_meta)[dst] = m;
+    if constexpr (NS == 1) {
+        a.sc_snap[dst] = a.snap[q];
+    } else {
+        // rebuild the double snapshot from the folded state
+        double2 w0 = ((const double2 *)a.sc_st[0])[dst], w1 = ((const double2 *)a.sc_st[1])[dst];
+        double zz, ww;
+        u4_to_dbl2(a.snap[(size_t)A.P + q], zz, ww);
+        a.sc_snap[dst] = dbl2_to_u4(w0.x, w0.y);
+        a.sc_snap[(size_t)A.P + dst] = dbl2_to_u4(w1.x, ww);
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_permute(const PermArgs a)
+{
+    constexpr int NS = Traits<P>::NS;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int wv = threadIdx.x >> 6;
+    const int total = a.items_pref[a.max_slots];
+    for (int item = blockIdx.x * wpb + wv; item < total; item += gridDim.x * wpb) {
+        const int s = find_item_slot(a.items_pref, a.max_slots, item);
+        if (!slot_selected(s, a.force_slot, a.need, a.ctl)) continue;
+        const RepDev rp = a.rep[s];
+        const int c = item - a.items_pref[s];
+        const int nd = rp.nd;
+        int ox[3], oy[3], oz[3], nx3;
+        if (nd == 1) {
+            ox[0] = oy[0] = oz[0] = 0;
+            nx3 = 1;
+        } else {
+            const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
+            int v[3][3] = {{(cx + nd - 1) % nd, cx, (cx + 1) % nd},
+                           {(cy + nd - 1) % nd, cy, (cy + 1) % nd},
+                           {(cz + nd - 1) % nd, cz, (cz + 1) % nd}};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { // sort three values ascending
+                int *u = v[d];
+                if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+                if (u[1] > u[2]) { int t = u[1]; u[1] = u[2]; u[2] = t; }
+                if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+            }
+            for (int k = 0; k < 3; ++k) { ox[k] = v[0][k]; oy[k] = v[1][k]; oz[k] = v[2][k]; }
+            nx3 = 3;
+        }
+        const int *cs = a.cs + rp.coff;
+        const int dst0 = a.cs_new[rp.coff + c];
+        int run = 0;
+        for (int kz = 0; kz < nx3; ++kz)
+            for (int ky = 0; ky < nx3; ++ky)
+                for (int kx = 0; kx < nx3; ++kx) {
+                    const int oc = ox[kx] + nd * (oy[ky] + nd * oz[kz]);
+                    const int q0 = cs[oc], q1 = cs[oc + 1];
+                    for (int qb = q0; qb < q1; qb += 64) {
+                        const int q = qb + lane;
+                        bool match = false;
+                        if (q < q1) {
+                            if (nd == 1) match = true;
+                            else if (NS == 2) {
+                                double x, y, z, w;
+                                u4_to_dbl2(a.snap[q], x, y);
+                                u4_to_dbl2(a.snap[(size_t)a.A.P + q], z, w);
+                                match = dbl_cell(x, y, z, rp.L, rp.invL, nd) == c;
+                            } else {
+                                uint4 X = a.snap[q];
+                                match = fixed_cell(X.x, X.y, X.z, nd) == c;
+                            }
+                        }
+                        unsigned long long bal = __ballot(match);
+                        if (match) {
+                            int rank = run + __popcll(bal & ((1ull << lane) - 1ull));
+                            fold_and_copy<P>(a, rp, q, dst0 + rank);
+                        }
+                        run += __popcll(bal);
+                    }
+                }
+        // every particle counted in this cell must have come from a
+        // neighbouring old cell; a shortfall means a particle jumped further
+        if (lane == 0 && run != a.cs_new[rp.coff + c + 1] - dst0) atomicOr(a.status + s, 4);
+    }
+}
+
+// ------------------------------------------------------------ k_build
+// One workgroup per row segment of cells: stage the neighbourhood in LDS,
+// build the canonical-order list of every member.
+#define BUILD_LDS_CAP 3072   // staged candidates (x 16 B = 48 KB, fixed point)
+#define BUILD_MAX_NX 18      // cells per staged row (width + 2 halo)
+
+template <int P, bool FROM_LDS>
+__device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &rp, int i,
+                                             int lx_m, const int (*tstart)[BUILD_MAX_NX],
+                                             const int (*tcnt)[BUILD_MAX_NX],
+                                             const int (*tglob)[BUILD_MAX_NX], int NX, bool full,
+                                             const uint4 *cand, int s, int nd)
+{
+    constexpr int NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    const size_t P_ = (size_t)A.P;
+    // member data
+    uint4 xi = a.src_x[i];
+    double xd = 0, yd = 0, zd = 0, wd = 0;
+    uint32_t meta;
+    if (NS == 2) {
+        u4_to_dbl2(xi, xd, yd);
+        u4_to_dbl2(a.src_x[P_ + i], zd, wd);
+        meta = meta_of_bits(wd);
+    } else meta = xi.w;
+    const int si = (int)(meta & SPECIES_MASK);
+    float rl2s[2];
+    double rl2d[2];
+    {
+        double u = (double)rp.sc;
+        rl2s[0] = (float)(a.pp.rl2d[si * 2] / (u * u));
+        rl2s[1] = (float)(a.pp.rl2d[si * 2 + 1] / (u * u));
+        rl2d[0] = a.pp.rl2d[si * 2];
+        rl2d[1] = a.pp.rl2d[si * 2 + 1];
+    }
+    int cnt = 0;
+    int *col = A.nbr_w + i;
+    const int cap = A.cap;
+    auto scan_cell = [&](int row, int lx) {
+        const int st = tstart[row][lx], n = tcnt[row][lx], g0 = tglob[row][lx];
+        for (int k = 0; k < n; ++k) {
+            bool acc;
+            if (NS == 2) {
+                double xj, yj, zj, wj;
+                if (FROM_LDS) {
+                    u4_to_dbl2(cand[2 * (st + k)], xj, yj);
+                    u4_to_dbl2(cand[2 * (st + k) + 1], zj, wj);
+                } else {
+                    u4_to_dbl2(a.src_x[st + k], xj, yj);
+                    u4_to_dbl2(a.src_x[P_ + st + k], zj, wj);
+                }
+                double dx = xd - xj, dy = yd - yj, dz = zd - zj;
+                dx -= rp.L * rint(dx * rp.invL);
+                dy -= rp.L * rint(dy * rp.invL);
+                dz -= rp.L * rint(dz * rp.invL);
+                double r2 = dx * dx + dy * dy + dz * dz;
+                int b = meta_of_bits(wj) & 1;
+                acc = r2 < rl2d[b];
+            } else {
+                uint4 xj = FROM_LDS ? cand[st + k] : a.src_x[st + k];
+                float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
+                      dz = (float)(int)(xi.z - xj.z);
+                float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                acc = r2 < rl2s[(xj.w & SPECIES_MASK) ? 1 : 0];
+            }
+            const int j = g0 + k;
+            if (acc && j != i) {
+                if (cnt < cap) col[(size_t)cnt * P_] = j;
+                ++cnt;
+            }
+        }
+    };
+    if (nd == 1) {
+        scan_cell(0, 0);
+    } else {
+        // own cell first, then each half-space offset and its opposite
+        scan_cell(4, lx_m);
+#pragma unroll 1
+        for (int k = 0; k < 13; ++k) {
+            int dx, dy, dz;
+            half_offset(k, dx, dy, dz);
+            for (int sgn = 1; sgn >= -1; sgn -= 2) {
+                int ddx = sgn * dx, ddy = sgn * dy, ddz = sgn * dz;
+                int row = (ddz + 1) * 3 + (ddy + 1);
+                int lx = full ? (lx_m + ddx + nd) % nd : lx_m + ddx;
+                scan_cell(row, lx);
+            }
+        }
+    }
+    A.nbr_cnt_w[i] = cnt < cap ? cnt : cap;
+    if (cnt > cap) atomicOr(a.status + s, 1);
+}
+
+template <int P>
+__device__ __forceinline__ void copy_back(const BuildArgs &a, int i)
+{
+    constexpr int NW = Traits<P>::NW, NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    const size_t P_ = (size_t)A.P;
+    if (a.from_scratch) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) A.st[w][i] = a.sc_st[w][i];
+        A.meta[i] = a.sc_meta[i];
+#pragma unroll
+        for (int w = 0; w < NS; ++w) {
+            uint4 x = a.src_x[w * P_ + i];
+            a.snap_cur[w * P_ + i] = x;
+            A.xref_w[w * P_ + i] = x;
+        }
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
+{
+    constexpr int NS = Traits<P>::NS;
+    __shared__ int tstart[9][BUILD_MAX_NX], tcnt[9][BUILD_MAX_NX], tglob[9][BUILD_MAX_NX];
+    __shared__ int sfits;
+    extern __shared__ uint4 cand[];
+    const int total = a.items_pref[a.max_slots];
+    const int T = blockDim.x, t = threadIdx.x;
+    const int cap_cand = a.lds_cap;
+    for (int it = remap_block(blockIdx.x, gridDim.x, a.xcd); it < total; it += gridDim.x) {
+        const int s = find_item_slot(a.items_pref, a.max_slots, it);
+        if (!slot_selected(s, a.force_slot, a.need, a.ctl)) continue;
+        const RepDev rp = a.rep[s];
+        const int nd = rp.nd;
+        const int item = it - a.items_pref[s];
+        const int *cs = a.cs_new + rp.coff;
+        int m0, m1, NX = 1, x0 = 0, cy = 0, cz = 0;
+        bool full = true;
+        if (nd == 1) {
+            m0 = rp.off + item * T;
+            m1 = min(m0 + T, rp.off + rp.n);
+            if (t == 0) {
+                tstart[0][0] = rp.off; tcnt[0][0] = rp.n; tglob[0][0] = rp.off;
+                if (item == 0 && a.from_scratch) { a.cs[rp.coff] = cs[0]; a.cs[rp.coff + 1] = cs[1]; }
+            }
+        } else {
+            const int W = a.width;
+            const int nseg = (nd <= W + 2) ? 1 : (nd + W - 1) / W;
+            const int seg = item % nseg, row = item / nseg;
+            cy = row % nd; cz = row / nd;
+            full = nd <= W + 2;
+            x0 = full ? 0 : seg * W;
+            const int xw = full ? nd : min(W, nd - x0);
+            NX = full ? nd : xw + 2;
+            const int rowbase = nd * (cy + nd * cz);
+            m0 = cs[rowbase + x0];
+            m1 = cs[rowbase + x0 + xw];
+            if (a.from_scratch) // retire the old cell starts of this segment
+                for (int k = t; k < xw; k += T) {
+                    a.cs[rp.coff + rowbase + x0 + k] = cs[rowbase + x0 + k];
+                    if (rowbase + x0 + k == nd * nd * nd - 1)
+                        a.cs[rp.coff + nd * nd * nd] = cs[nd * nd * nd];
+                }
+            for (int k = t; k < 9 * NX; k += T) {
+                int rw = k / NX, lx = k % NX;
+                int dz = rw / 3 - 1, dy = rw % 3 - 1;
+                int gx = full ? lx : (x0 - 1 + lx + nd) % nd;
+                int gy = (cy + dy + nd) % nd, gz = (cz + dz + nd) % nd;
+                int cc = gx + nd * (gy + nd * gz);
+                tglob[rw][lx] = cs[cc];
+                tcnt[rw][lx] = cs[cc + 1] - cs[cc];
+            }
+        }
+        __syncthreads();
+        if (t == 0) { // LDS offsets of the staged cells
+            int acc = 0;
+            for (int rw = 0; rw < (nd == 1 ? 1 : 9); ++rw)
+                for (int lx = 0; lx < NX; ++lx) { tstart[rw][lx] = acc; acc += tcnt[rw][lx]; }
+            sfits = acc <= cap_cand;
+            if (!sfits) // fall back to global reads: start = global index
+                for (int rw = 0; rw < (nd == 1 ? 1 : 9); ++rw)
+                    for (int lx = 0; lx < NX; ++lx) tstart[rw][lx] = tglob[rw][lx];
+        }
+        __syncthreads();
+        const bool fits = sfits != 0;
+        if (fits) { // stage: each cell's particles are contiguous in the arena
+            const int nrow = nd == 1 ? 1 : 9;
+            for (int rw = 0; rw < nrow; ++rw)
+                for (int lx = 0; lx < NX; ++lx) {
+                    const int g0 = tglob[rw][lx], n = tcnt[rw][lx], l0 = tstart[rw][lx];
+                    for (int k = t; k < n; k += T) {
+                        if (NS == 2) {
+                            cand[2 * (l0 + k)] = a.src_x[g0 + k];
+                            cand[2 * (l0 + k) + 1] = a.src_x[(size_t)a.A.P + g0 + k];
+                        } else cand[l0 + k] = a.src_x[g0 + k];
+                    }
+                }
+        }
+        __syncthreads();
+        for (int i = m0 + t; i < m1; i += T) {
+            int lx_m = 0;
+            if (nd > 1) { // the member's cell is the own-row cell whose range holds i
+                int gx = full ? 0 : x0;
+                const int xe = full ? nd - 1 : min(x0 + a.width, nd) - 1;
+                const int rowbase = nd * (cy + nd * cz);
+                while (gx < xe && cs[rowbase + gx + 1] <= i) ++gx;
+                lx_m = full ? gx : gx - x0 + 1;
+            }
+            if (fits) build_member<P, true>(a, rp, i, lx_m, tstart, tcnt, tglob, NX, full, cand, s, nd);
+            else build_member<P, false>(a, rp, i, lx_m, tstart, tcnt, tglob, NX, full, cand, s, nd);
+            copy_back<P>(a, i);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ k_obs_reduce
+// Per slot: fixed-order FP64 sums of e_i, w_i, v^2 and v.
+__global__ void __launch_bounds__(256) k_obs_reduce(const ObsArgs a)
+{
+    const int s = blockIdx.x;
+    if (s >= a.max_slots || !a.ctl[s].z) return;
+    const RepDev rp = a.rep[s];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < rp.n; k += blockDim.x) {
+        const double *o = a.obs + (size_t)(rp.off + k) * 8;
+        acc[0] += o[3];
+        acc[1] += o[4];
+        acc[2] += o[5] * o[5] + o[6] * o[6] + o[7] * o[7];
+        acc[3] += o[5];
+        acc[4] += o[6];
+        acc[5] += o[7];
+    }
+    __shared__ double red[6][256];
+    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) a.out[s * 8 + q] = red[q][0];
+}
+
+// ------------------------------------------------------------ k_scale_vel
+template <int P>
+__global__ void k_scale_vel(const ScaleArgs a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int i = a.off + k;
+    State<P> st;
+    st.load(a.A, i);
+    if constexpr (P == PREC_DS) {
+        dsf f = {a.f_hi, a.f_lo};
+        st.vx = ds_mul(st.vx, f); st.vy = ds_mul(st.vy, f); st.vz = ds_mul(st.vz, f);
+    } else if constexpr (P == PREC_FP32) {
+        st.vx *= a.ff; st.vy *= a.ff; st.vz *= a.ff;
+    } else {
+        st.vx *= a.fd; st.vy *= a.fd; st.vz *= a.fd;
+    }
+    st.store(a.A, i);
+}
+
+// ------------------------------------------------------------ k_ds_eval
+__global__ void k_ds_eval(int op, long long n, const float *a, const float *b, float *out)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (op == 3) { // compensated sum of a[k].hi, single workgroup, fixed order
+        if (blockIdx.x != 0 || threadIdx.x != 0) return;
+        sum2f s;
+        s.init();
+        for (long long q = 0; q < n; ++q) s.add(a[2 * q]);
+        dsf r = s.result();
+        out[0] = r.hi;
+        out[1] = r.lo;
+        return;
+    }
+    if (k >= n) return;
+    dsf x = {a[2 * k], a[2 * k + 1]}, y = {b[2 * k], b[2 * k + 1]}, r;
+    if (op == 0) r = ds_add(x, y);
+    else if (op == 1) r = ds_sub(x, y);
+    else r = ds_mul(x, y);
+    out[2 * k] = r.hi;
+    out[2 * k + 1] = r.lo;
+}
+
+// ------------------------------------------------------------ launchers
+#define LAUNCH_CHECK() return hipGetLastError()
+
+template <int P>
+static hipError_t launch_step_t(const StepArgs &a, int block, bool obs, hipStream_t s)
+{
+    int grid = (a.A.P + block - 1) / block;
+    if (obs) hipLaunchKernelGGL((k_step<P, true>), dim3(grid), dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, false>), dim3(grid), dim3(block), 0, s, a);
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_step(int prec, const StepArgs &a, int block, bool obs, hipStream_t s)
+{
+    switch (prec) {
+    case PREC_FP32: return launch_step_t<PREC_FP32>(a, block, obs, s);
+    case PREC_DS: return launch_step_t<PREC_DS>(a, block, obs, s);
+    case PREC_MIX: return launch_step_t<PREC_MIX>(a, block, obs, s);
+    default: return launch_step_t<PREC_FP64>(a, block, obs, s);
+    }
+}
+
+hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s)
+{
+    int grid = (a.P + 255) / 256;
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL((k_count<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_count<PREC_FP32>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan, dim3(a.max_slots), dim3(1024), 0, s, a);
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_permute(int prec, const PermArgs &a, int grid, hipStream_t s)
+{
+    switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((k_permute<PREC_FP32>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_DS: hipLaunchKernelGGL((k_permute<PREC_DS>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_MIX: hipLaunchKernelGGL((k_permute<PREC_MIX>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_permute<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipStream_t s)
+{
+    size_t lds = (size_t)a.lds_cap * 16 * (prec == PREC_FP64 ? 2 : 1);
+    switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((k_build<PREC_FP32>), dim3(grid), dim3(block), lds, s, a); break;
+    case PREC_DS: hipLaunchKernelGGL((k_build<PREC_DS>), dim3(grid), dim3(block), lds, s, a); break;
+    case PREC_MIX: hipLaunchKernelGGL((k_build<PREC_MIX>), dim3(grid), dim3(block), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_build<PREC_FP64>), dim3(grid), dim3(block), lds, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_obs_reduce(const ObsArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_obs_reduce, dim3(a.max_slots), dim3(256), 0, s, a);
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_scale_vel(int prec, const ScaleArgs &a, hipStream_t s)
+{
+    int grid = (a.n + 255) / 256;
+    if (grid == 0) return hipSuccess;
+    switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((k_scale_vel<PREC_FP32>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_DS: hipLaunchKernelGGL((k_scale_vel<PREC_DS>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_MIX: hipLaunchKernelGGL((k_scale_vel<PREC_MIX>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_scale_vel<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_ds_eval(int op, long long n, const float *a, const float *b, float *out, hipStream_t s)
+{
+    long long grid = op == 3 ? 1 : (n + 255) / 256;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ds_eval, dim3((unsigned)grid), dim3(256), 0, s, op, n, a, b, out);
+    LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------ control pokes
+// Stream-ordered writes of control words (graph- and capture-safe; no host
+// buffers whose lifetime would have to outlast an asynchronous copy).
+__global__ void k_add_targets(int *target, const Ctl *ctl, int max_slots, int delta)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < max_slots && ctl[s].z) target[s] += delta;
+}
+
+__global__ void k_poke(int *p, int v) { *p = v; }
+
+hipError_t launch_add_targets(int *target, const Ctl *ctl, int max_slots, int delta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_targets, dim3((max_slots + 255) / 256), dim3(256), 0, s, target, ctl, max_slots, delta);
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_poke(int *p, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_poke, dim3(1), dim3(1), 0, s, p, v);
+    LAUNCH_CHECK();
+}

@@ -1,0 +1,110 @@
+// Kernel argument blocks and launchers of libmdx (shared by kernels.hip and
+// the host engine).  Every argument block is passed by value.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "md_dev.hpp"
+
+struct KArena {
+    int P;            // arena stride (particle slots)
+    int cap;          // neighbour-list capacity per particle
+    uint4 *st[3];     // state words
+    const uint4 *xref;
+    uint4 *xref_w;    // same memory as xref
+    int4 *meta;
+    const int *nbr;
+    int *nbr_w;       // same memory as nbr
+    const int *nbr_cnt;
+    int *nbr_cnt_w;   // same memory as nbr_cnt
+};
+
+struct StepArgs {
+    KArena A;
+    int cell_cap, max_slots, xcd, pad0;
+    const uint4 *snap_cur;
+    uint4 *snap_next;
+    const RepDev *rep;
+    const Ctl *ctl_cur;
+    Ctl *ctl_next;
+    const int *target;
+    int *need_cur, *need_other;
+    int *count_cur, *count_other;
+    int *status;
+    double *obs;
+    PairDev pp;
+    IntegDev ig;
+};
+
+struct CountArgs {
+    int P, max_slots, force_slot, pad0;
+    const uint4 *snap;
+    const RepDev *rep;
+    const Ctl *ctl;
+    int *count;
+};
+
+struct ScanArgs {
+    int max_slots, force_slot;
+    const RepDev *rep;
+    const int *need;
+    const Ctl *ctl;
+    const int *count;
+    int *cs_new;
+    int *status;
+    int *nreb;
+};
+
+struct PermArgs {
+    KArena A;
+    int max_slots, force_slot;
+    const int *items_pref;
+    const RepDev *rep;
+    const int *need;
+    const Ctl *ctl;
+    const int *cs, *cs_new;
+    const uint4 *snap;
+    uint4 *sc_st[3];
+    uint4 *sc_snap;
+    int4 *sc_meta;
+    int *status;
+};
+
+struct BuildArgs {
+    KArena A;
+    int max_slots, force_slot, from_scratch, width, lds_cap, xcd;
+    const int *items_pref;
+    const RepDev *rep;
+    const int *need;
+    const Ctl *ctl;
+    int *cs;
+    const int *cs_new;
+    const uint4 *src_x;
+    uint4 *snap_cur;
+    const uint4 *sc_st[3];
+    const int4 *sc_meta;
+    int *status;
+    PairDev pp;
+};
+
+struct ObsArgs {
+    int max_slots, pad0;
+    const RepDev *rep;
+    const Ctl *ctl;
+    const double *obs;
+    double *out; // [max_slots][8]
+};
+
+struct ScaleArgs {
+    KArena A;
+    int off, n;
+    float f_hi, f_lo, ff, pad0;
+    double fd;
+};
+
+hipError_t launch_step(int prec, const StepArgs &a, int block, bool obs, hipStream_t s);
+hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+hipError_t launch_permute(int prec, const PermArgs &a, int grid, hipStream_t s);
+hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_obs_reduce(const ObsArgs &a, hipStream_t s);
+hipError_t launch_scale_vel(int prec, const ScaleArgs &a, hipStream_t s);
+hipError_t launch_ds_eval(int op, long long n, const float *a, const float *b, float *out, hipStream_t s);

@@ -1,0 +1,155 @@
+// Device-side data layout, per-precision traits and the small helpers shared
+// by the kernels and the host engine of libmdx.
+//
+// HBM layout (one particle arena of P slots, structure of arrays, every
+// per-particle record a multiple of 16 bytes so that loads are dwordx4):
+//   state word k  : uint4 st[k][P]   (k < NW; precision-dependent packing)
+//   snapshot      : uint4 snap[2][NS][P]  ping-pong, read by neighbours
+//   reference pos : uint4 xref[NS][P]     positions at the last list build
+//   meta          : int4 meta[P]          (image x, image y, image z, id)
+//   list count    : int nbr_cnt[P];  list: int nbr[cap][P] (column-major)
+//   observation   : double obs[P][8]      (fx, fy, fz, e_i, w_i, vx, vy, vz)
+// plus a scratch copy of st/snap/meta used by the cell sort.
+//
+// The snapshot is what neighbours gather every step.  For the FP32, DS and
+// MIXED64 paths it is a 32-bit fixed-point copy of the position,
+// X = round(x * 2^32 / L) mod 2^32, so that the minimum image is the int32
+// wrap-around of X_i - X_j and a pair separation is exact before it is
+// converted to float.  Its w word holds (slot << 4) | species.  The FP64
+// path keeps double positions (two words: x,y | z,w) and the textbook
+// minimum image.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "ds.hpp"
+
+enum { PREC_FP32 = 0, PREC_DS = 1, PREC_MIX = 2, PREC_FP64 = 3 };
+
+template <int P> struct Traits;
+template <> struct Traits<PREC_FP32> { static constexpr int NW = 2, NS = 1; };
+template <> struct Traits<PREC_DS> { static constexpr int NW = 3, NS = 1; };
+template <> struct Traits<PREC_MIX> { static constexpr int NW = 3, NS = 1; };
+template <> struct Traits<PREC_FP64> { static constexpr int NW = 3, NS = 2; };
+
+// Replica (slot) geometry, one entry per slot in device memory.
+struct RepDev {
+    int n;        // particles
+    int off;      // first particle slot in the arena
+    int nd;       // cells per box edge (1 = single-cell mode)
+    int coff;     // first cell in the cell arena (nd^3 + 1 entries reserved)
+    double L;     // box edge
+    double invL;  // 1 / L
+    double fxs;   // 2^32 / L   (double -> fixed point)
+    float sc;     // L / 2^32   (fixed point unit in length units)
+    float Lf;     // L rounded to float (FP32 wrap)
+    float L_hi, L_lo; // L as double-single
+    int items3, items4; // work items of the sort and list-build kernels
+};
+
+// Control word of a slot: x = completed steps, y = 1 if velocities are at a
+// full step, z = 1 if attached.  Double-buffered by step parity.
+typedef int4 Ctl;
+
+// Pair table in float and double, indexed [si*2+sj].
+struct PairDev {
+    float rl2[4];    // list radius^2 = (rc + skin)^2
+    float rc2[4];
+    float sig2[4];
+    float eps24[4];  // 24 eps
+    float eps4[4];   // 4 eps
+    float shift[4];  // V_LJ(rc)
+    double rl2d[4], rc2d[4], sig2d[4], eps24d[4], eps4d[4], shiftd[4];
+    float hs2;       // (skin/2)^2
+    double hs2d;
+    int nsp;
+};
+
+// Integration constants (dt and dt/2m) in every representation.
+struct IntegDev {
+    double dt, h;       // h = dt / (2 m)
+    float dtf, hf;
+    float dt_hi, dt_lo, h_hi, h_lo;
+    double m;
+};
+
+// FP64 snapshots carry the meta word as the raw bits of their fourth double.
+__host__ __device__ __forceinline__ uint32_t meta_of_bits(double w)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return (uint32_t)(unsigned long long)__double_as_longlong(w);
+#else
+    unsigned long long b;
+    __builtin_memcpy(&b, &w, 8);
+    return (uint32_t)b;
+#endif
+}
+__host__ __device__ __forceinline__ double bits_of_meta(uint32_t m)
+{
+    unsigned long long b = 0xFFFFFFFF00000000ull | m;
+#ifdef __HIP_DEVICE_COMPILE__
+    return __longlong_as_double((long long)b);
+#else
+    double w;
+    __builtin_memcpy(&w, &b, 8);
+    return w;
+#endif
+}
+
+#define SLOT_SHIFT 4
+#define SPECIES_MASK 1u
+#define NO_SLOT 0xFFFFFFFFu
+
+// ---------------------------------------------------------------- fixed point
+__host__ __device__ __forceinline__ uint32_t to_fixed(double x, double fxs)
+{
+    double t = x * fxs;
+#ifdef __HIP_DEVICE_COMPILE__
+    long long k = __double2ll_rn(t);
+#else
+    long long k = llrint(t);
+#endif
+    return (uint32_t)(unsigned long long)k;
+}
+
+__host__ __device__ __forceinline__ uint32_t fixed_cell1(uint32_t X, uint32_t nd)
+{
+    return (uint32_t)(((unsigned long long)X * nd) >> 32);
+}
+
+__host__ __device__ __forceinline__ int fixed_cell(uint32_t X, uint32_t Y, uint32_t Z, int nd)
+{
+    return (int)(fixed_cell1(X, nd) + (uint32_t)nd * (fixed_cell1(Y, nd) + (uint32_t)nd * fixed_cell1(Z, nd)));
+}
+
+// FP64 path: cell of a double position (wrapped into [0, L) first).
+__host__ __device__ __forceinline__ int dbl_cell1(double x, double L, double invL, int nd)
+{
+    double w = x - L * floor(x * invL);
+    int c = (int)(w * invL * (double)nd);
+    if (c < 0) c = 0;
+    if (c >= nd) c = nd - 1;
+    return c;
+}
+
+__host__ __device__ __forceinline__ int dbl_cell(double x, double y, double z, double L, double invL, int nd)
+{
+    return dbl_cell1(x, L, invL, nd) + nd * (dbl_cell1(y, L, invL, nd) + nd * dbl_cell1(z, L, invL, nd));
+}
+
+// The 13 half-space cell offsets; a neighbour search visits the own cell and
+// then each offset o followed by -o ("opposite cell order", Sec. 4.1).
+__host__ __device__ __forceinline__ void half_offset(int k, int &dx, int &dy, int &dz)
+{
+    // k in [0,13): enumerate (dz, dy, dx) lexicographically, keep the half
+    // space dz > 0 or (dz == 0 and (dy > 0 or (dy == 0 and dx > 0))).
+    int cnt = 0;
+    for (int z = -1; z <= 1; ++z)
+        for (int y = -1; y <= 1; ++y)
+            for (int x = -1; x <= 1; ++x) {
+                bool pos = z > 0 || (z == 0 && (y > 0 || (y == 0 && x > 0)));
+                if (!pos) continue;
+                if (cnt == k) { dx = x; dy = y; dz = z; return; }
+                ++cnt;
+            }
+    dx = dy = dz = 0;
+}

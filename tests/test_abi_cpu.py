@@ -1,0 +1,73 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/md.h declares, and its host-only sizing/validation behaves."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import md_inputs as I
+from paper_0912_3824_amd import mdx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "md.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(mdx.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mdx.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.md_abi_version() == 1
+
+
+def _cfg(prec="ds", **kw):
+    return mdx.make_config(I.ka_table(), prec, 0.001, 0.3, kw.pop("slots", 1),
+                           kw.pop("n", 64000), **kw)
+
+
+def test_workspace_bytes_scales_with_precision_and_size():
+    b = {p: mdx.md_workspace_bytes(_cfg(p)) for p in mdx.PRECISIONS}
+    assert all(v > 0 for v in b.values())
+    assert b["fp32"] < b["ds"] <= b["fp64"]
+    small, big = mdx.md_workspace_bytes(_cfg(n=1000)), mdx.md_workspace_bytes(_cfg(n=100000))
+    assert big > 50 * small
+    # about 0.6-1 KB per particle at KA density (lists dominate)
+    per = mdx.md_workspace_bytes(_cfg(n=1000000)) / 1e6
+    assert 400 < per < 1500
+
+
+def test_validation_rejects_bad_configs():
+    lib = mdx.load()
+    good = _cfg()
+    assert mdx.md_validate(good) == 0
+    for field, val in [("n_species", 3), ("precision", 7), ("dt", 0.0), ("skin", -1.0),
+                       ("max_slots", 0), ("max_particles", 0), ("mass", 0.0)]:
+        c = _cfg()
+        setattr(c, field, val)
+        assert mdx.md_validate(c) == -1, field
+        assert mdx.md_workspace_bytes(c) == -1
+    c = _cfg()
+    c.eps[1] = 2.0   # asymmetric table
+    assert mdx.md_validate(c) == -1
+    # box must hold twice the largest list radius (2.5 + 0.3)
+    assert mdx.md_validate(good, 100, 5.59) == -2
+    assert mdx.md_validate(good, 100, 5.61) == 0
+    assert mdx.md_validate(good, 0, 10.0) == -1
+    assert lib.md_strerror(-2) == b"box shorter than twice the list radius"
+
+
+def test_create_rejects_missing_workspace_without_gpu():
+    lib = mdx.load()
+    c = _cfg()
+    h = ctypes.c_void_p()
+    assert lib.md_create(ctypes.byref(c), None, 0, None, ctypes.byref(h)) == -3
+    assert lib.md_create(ctypes.byref(c), ctypes.c_void_p(0x1001), 1 << 40, None, ctypes.byref(h)) == -3

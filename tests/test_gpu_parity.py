@@ -1,0 +1,146 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Inputs are seeded KA / LJ systems (fcc-subset starts with a small jitter so
+that no lattice shell sits on a cutoff).  The oracle always receives the
+state the device holds (md_get_state), so the comparison isolates the
+device arithmetic.  Sizes span several cells per edge, several workgroups
+and a ragged tail (N not a multiple of the block size)."""
+import math
+
+import numpy as np
+import pytest
+
+import md_inputs as I
+from oracle import oracle as O
+from gpu_helpers import (BAND, TOL_E, TOL_F, force_error, near_cutoff, pool_for,
+                         say)
+
+pytestmark = pytest.mark.gpu
+PRECS = ["fp32", "ds", "mixed64", "fp64"]
+
+
+def _ka(n, T=0.7, seed=11, jitter=0.06):
+    return I.make_ka(n, T, jitter=jitter, seed=seed)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [500, 3001, 12007])
+def test_forces_match_oracle(prec, n):
+    s = _ka(n)
+    say("forces", prec, n)
+    pool = pool_for([s], prec)
+    pos, vel, img = pool.get_state(0)
+    f, e = pool.forces(0)
+    fr, er, wr = O.forces(pos, s.box, s.species, s.table)
+    excl = None
+    if prec != "fp64":
+        excl = near_cutoff(pos, s.box, s.species, s.table, lambda a, b: s.table.rcut[a, b])
+    err, frms = force_error(f, fr, excl)
+    say("  e_F", err, "F_rms", frms, "excluded", 0 if excl is None else int(excl.sum()))
+    assert err < TOL_F[prec]
+    assert abs(e.sum() - er.sum()) <= TOL_E[prec] * abs(er.sum())
+    if excl is not None and excl.any():  # one cutoff jump at most
+        jump = abs(O.pair(s.table.rcut[0, 0] * (1 - 1e-12), 1.5, 0.8, 2.0)[1])
+        assert np.abs(f - fr)[excl].max() < 2 * jump + TOL_F[prec] * frms
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,width", [(500, 4), (3001, 1), (3001, 4), (12007, 2)])
+def test_neighbour_lists_match_oracle(prec, n, width):
+    s = _ka(n)
+    say("lists", prec, n, width)
+    pool = pool_for([s], prec)
+    if width != 4:
+        pool.set_launch(build_width=width)
+        pool.rebuild_neighbours()
+    pos, vel, img = pool.get_state(0)
+    cnt, ids = pool.neighbours(0, cap=256)
+    ref = O.neighbours(pos, s.box, s.species, s.table, s.skin)
+    amb = near_cutoff(pos, s.box, s.species, s.table,
+                      lambda a, b: s.table.rcut[a, b] + s.skin, band=1e-6)
+    bad = 0
+    for i in range(n):
+        got = set(ids[i, :cnt[i]].tolist())
+        if got != set(ref[i].tolist()):
+            assert amb[i], (i, sorted(got ^ set(ref[i].tolist())))
+            bad += 1
+        assert len(got) == cnt[i]  # no duplicates
+    say("  ambiguous-band particles differing:", bad)
+    assert bad <= max(1, n // 10000)
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ten_step_trajectory(prec):
+    s = _ka(3001, T=0.7)
+    say("10-step", prec)
+    pool = pool_for([s], prec)
+    p0, v0, i0 = pool.get_state(0)
+    pool.step(10)
+    p1, v1, i1 = pool.get_state(0)
+    pr, vr, ir, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 10)
+    d = (p1 + i1 * s.box) - (pr + (ir + i0) * s.box)
+    dv = np.abs(v1 - vr).max()
+    say("  max|dr|", np.abs(d).max(), "max|dv|", dv)
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert np.abs(d).max() < tol
+    assert dv < tol
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+def test_long_run_with_rebuilds(prec):
+    """300 steps from a jittered lattice (several list rebuilds and cell
+    re-sorts) against the oracle's brute-force integrator."""
+    s = _ka(1500, T=1.0, jitter=0.1, seed=4)
+    say("300-step", prec)
+    pool = pool_for([s], prec)
+    p0, v0, i0 = pool.get_state(0)
+    pool.step(300)
+    obs = pool.observables()[0]
+    p1, v1, i1 = pool.get_state(0)
+    pr, vr, ir, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 300)
+    d = np.abs((p1 + i1 * s.box) - (pr + (ir + i0) * s.box)).max()
+    say("  rebuilds", obs["n_rebuilds"], "max|dr|", d)
+    assert obs["n_rebuilds"] >= 3
+    assert obs["step"] == 300 and obs["status"] == 0
+    assert d < (1e-8 if prec == "fp64" else 1e-4)
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_observables_match_oracle(prec):
+    s = _ka(3001, T=0.7)
+    say("observables", prec)
+    pool = pool_for([s], prec)
+    pool.step(5)
+    o = pool.observables()[0]
+    pos, vel, _ = pool.get_state(0)
+    r = O.observables(pos, vel, s.box, s.species, s.table)
+    tol = TOL_E[prec]
+    for k in ("epot", "virial"):
+        assert o[k] == pytest.approx(r[k], rel=tol), k
+    assert o["ekin"] == pytest.approx(r["ekin"], rel=1e-12)
+    assert np.abs(o["momentum"] - r["momentum"]).max() < 1e-9
+    assert o["pressure"] == pytest.approx(r["pressure"], rel=tol * 10)
+    pool.close()
+
+
+def test_lj_fp64_1000_steps():
+    """Single-species LJ, N = 4000 on an fcc lattice, rho 0.8442, T 1.5, FP64
+    plain path: 1000 steps against the oracle."""
+    s = I.make_lj(4000)
+    say("lj4000 fp64 1000 steps")
+    pool = pool_for([s], "fp64")
+    p0, v0, i0 = pool.get_state(0)
+    o0 = pool.observables()[0]
+    pool.step(1000)
+    o1 = pool.observables()[0]
+    p1, v1, i1 = pool.get_state(0)
+    pr, vr, ir, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 1000)
+    d = np.abs((p1 + i1 * s.box) - (pr + (ir + i0) * s.box)).max()
+    say("  max|dr|", d, "dE", o1["etot"] - o0["etot"])
+    assert d < 1e-6
+    assert abs(o1["etot"] - o0["etot"]) < 1e-3 * abs(o0["etot"])
+    pool.close()

@@ -79,6 +79,8 @@ typedef enum {
 #define MD_ST_LIST_OVERFLOW 1 /* a particle had more neighbours than nbr_capacity */
 #define MD_ST_NONFINITE 2     /* a position became NaN/Inf */
 #define MD_ST_LOST 4          /* cell counting lost particles (follows NONFINITE) */
+#define MD_ST_NO_PAD 8        /* a list could not be padded: every particle of the
+                                 replica lies within the list radius of another */
 #define MD_ST_AT_FULL_STEP 256 /* not an error: velocities are at a full step
                                   (reported by md_poll only) */
 
@@ -123,6 +125,7 @@ typedef struct {
     double momentum[3]; /* m sum_i v_i */
     int64_t step;       /* steps completed since attach */
     int64_t n_rebuilds; /* neighbour-list builds since attach (incl. the first) */
+    int64_t list_entries; /* sum of the Verlet-list lengths of the replica */
     int32_t status;     /* MD_ST_* bits */
     int32_t n;          /* particles (0 if the slot is empty) */
 } md_obs;
@@ -226,6 +229,14 @@ md_status md_observables(md_system *sys, md_obs *out);
 /* Multiply the velocities of a replica by `factor` (velocity rescaling for
  * host-driven equilibration).  Asynchronous. */
 md_status md_scale_velocities(md_system *sys, int32_t slot, double factor);
+
+/* Benchmark helper: advance every attached replica by n_steps like md_step
+ * but with eager launches, timing each step's fused kernel and its group of
+ * rebuild kernels with hipEvents recorded on the pool's stream.  out[5]:
+ * [0] mean fused-kernel ms, [1] mean rebuild-group ms over all steps,
+ * [2] mean rebuild-group ms over steps in which a replica rebuilt,
+ * [3] number of such steps, [4] total GPU ms of the n_steps.  Synchronises. */
+md_status md_profile_steps(md_system *sys, int64_t n_steps, double *out);
 
 /* Block until all work on the pool's stream has finished. */
 md_status md_sync(md_system *sys);

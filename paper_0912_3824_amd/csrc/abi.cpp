@@ -98,7 +98,8 @@ struct md_system {
     RepDev *rep = nullptr;
     Ctl *ctl[2]{};
     int *target = nullptr, *need[2]{}, *status = nullptr, *nreb = nullptr;
-    int *items3 = nullptr, *items4 = nullptr;
+    int *items3 = nullptr, *items4 = nullptr, *chunks = nullptr;
+    double *partial = nullptr;
     // host state
     PairDev pp{};
     IntegDev ig{};
@@ -184,7 +185,7 @@ static Layout layout_of(const md_config *c)
     L.P = align_up(c->max_particles, 256);
     double rho = c->max_density > 0 ? c->max_density : 1.2;
     double rl = rlist_max_of(c);
-    if (c->nbr_capacity > 0) L.cap = c->nbr_capacity;
+    if (c->nbr_capacity > 0) L.cap = align_up(c->nbr_capacity, 8);
     else {
         double mean = 4.18879020478639 * rl * rl * rl * rho; // (4/3) pi r^3 rho
         L.cap = align_up((int64_t)std::ceil(1.3 * mean + 16.0), 8);
@@ -237,6 +238,8 @@ static int64_t carve(md_system *s, const Layout &L, char *base)
     d->nreb = c.take<int>(L.slots);
     d->items3 = c.take<int>(L.slots + 1);
     d->items4 = c.take<int>(L.slots + 1);
+    d->chunks = c.take<int>(L.slots + 1);
+    d->partial = c.take<double>((L.P / 4096 + L.slots + 1) * 8);
     d->obs_out = c.take<double>(L.slots * 8);
     return align_up(c.off, ALIGN);
 }
@@ -263,6 +266,17 @@ static void make_tables(md_system *s)
         p.eps24[t] = (float)p.eps24d[t];
         p.eps4[t] = (float)p.eps4d[t];
         p.shift[t] = (float)p.shiftd[t];
+    }
+    // uniform cutoff ratio: rc_ab / sigma_ab equal (to rounding) for every pair
+    {
+        const int k = c->n_species;
+        const double r0 = c->rcut[0] / c->sigma[0];
+        bool uni = true;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                if (std::fabs(c->rcut[a * 2 + b] / c->sigma[a * 2 + b] - r0) > 1e-12 * r0) uni = false;
+        p.uniform = uni ? 1 : 0;
+        p.s2cut = (float)(1.0 / (r0 * r0));
     }
     p.hs2d = 0.25 * c->skin * c->skin;
     p.hs2 = (float)p.hs2d;
@@ -298,17 +312,20 @@ static int items4_of(const md_system *s, int n, int nd)
 static md_status upload_items(md_system *s)
 {
     int S = (int)s->lay.slots;
-    std::vector<int> p3(S + 1, 0), p4(S + 1, 0);
+    std::vector<int> p3(S + 1, 0), p4(S + 1, 0), p5(S + 1, 0);
     for (int k = 0; k < S; ++k) {
         const SlotHost &h = s->slots[k];
-        int a3 = 0, a4 = 0;
+        int a3 = 0, a4 = 0, a5 = 0;
         if (h.attached) {
             a3 = h.nd * h.nd * h.nd;
             a4 = items4_of(s, h.n, h.nd);
+            a5 = (h.n + 4095) / 4096;
         }
         p3[k + 1] = p3[k] + a3;
         p4[k + 1] = p4[k] + a4;
+        p5[k + 1] = p5[k] + a5;
     }
+    HIPCHK(s, hipMemcpyAsync(s->chunks, p5.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->items3, p3.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->items4, p4.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -759,11 +776,11 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     s->ws = (char *)workspace;
     s->ws_bytes = ws_bytes;
     carve(s, L, s->ws);
-    s->launch.step_block = 256;
-    s->launch.build_width = 4;
+    s->launch.step_block = 512;
+    s->launch.build_width = 8;
     s->launch.build_block = 256;
     s->launch.graph_steps = 32;
-    s->launch.xcd_remap = 1;
+    s->launch.xcd_remap = 0;
     make_tables(s);
     s->slots.assign(L.slots, SlotHost());
     s->parena.reset(L.P);
@@ -1007,6 +1024,9 @@ md_status md_observables(md_system *s, md_obs *out)
     oa.rep = s->rep;
     oa.ctl = s->ctl[s->parity];
     oa.obs = s->obs;
+    oa.nbr_cnt = s->nbr_cnt;
+    oa.chunk_pref = s->chunks;
+    oa.partial = s->partial;
     oa.out = s->obs_out;
     HIPCHK(s, launch_obs_reduce(oa, s->stream));
     std::vector<double> r((size_t)S * 8);
@@ -1032,6 +1052,7 @@ md_status md_observables(md_system *s, md_obs *out)
         o.pressure = (2.0 * o.ekin + o.virial) / (3.0 * V);
         for (int d = 0; d < 3; ++d) o.momentum[d] = m * r[8 * k + 3 + d];
         o.step = c[k].x;
+        o.list_entries = (int64_t)r[8 * k + 6];
         o.n_rebuilds = nr[k];
         o.status = stv[k];
     }
@@ -1054,6 +1075,59 @@ md_status md_scale_velocities(md_system *s, int32_t slot, double factor)
     a.ff = (float)factor;
     a.fd = factor;
     HIPCHK(s, launch_scale_vel(s->prec, a, s->stream));
+    return MD_OK;
+}
+
+md_status md_profile_steps(md_system *s, int64_t n_steps, double *out)
+{
+    if (!s || !out) return MD_E_ARG;
+    if (n_steps < 1 || n_steps > (1LL << 24)) return fail(s, MD_E_ARG, "n_steps out of range");
+    for (auto &h : s->slots)
+        if (h.attached) h.target += n_steps;
+    HIPCHK(s, launch_add_targets(s->target, s->ctl[s->parity], (int)s->lay.slots, (int)n_steps, s->stream));
+    hipEvent_t ev[3];
+    for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
+    const int S = (int)s->lay.slots;
+    std::vector<int> nr(S);
+    auto nreb_sum = [&](long long &tot) -> md_status {
+        HIPCHK(s, hipMemcpyAsync(nr.data(), s->nreb, 4 * S, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        tot = 0;
+        for (int v : nr) tot += v;
+        return MD_OK;
+    };
+    long long prev = 0, cur = 0;
+    md_status st = nreb_sum(prev);
+    double t_step = 0, t_reb = 0, t_reb_hit = 0, n_hit = 0, t_tot = 0;
+    for (int64_t k = 0; k <= n_steps && st == MD_OK; ++k) { // last launch finalises
+        const int p = s->parity;
+        StepArgs a = step_args(s, p);
+        HIPCHK(s, hipEventRecord(ev[0], s->stream));
+        HIPCHK(s, launch_step(s->prec, a, s->launch.step_block, false, s->stream));
+        HIPCHK(s, hipEventRecord(ev[1], s->stream));
+        st = launch_rebuild(s, p, -1, true);
+        HIPCHK(s, hipEventRecord(ev[2], s->stream));
+        s->parity ^= 1;
+        if (st != MD_OK) break;
+        HIPCHK(s, hipEventSynchronize(ev[2]));
+        float a01 = 0, a12 = 0;
+        HIPCHK(s, hipEventElapsedTime(&a01, ev[0], ev[1]));
+        HIPCHK(s, hipEventElapsedTime(&a12, ev[1], ev[2]));
+        if ((st = nreb_sum(cur)) != MD_OK) break;
+        if (k == n_steps) break; // the finalising launch is not a step
+        t_step += a01;
+        t_reb += a12;
+        t_tot += a01 + a12;
+        if (cur != prev) { t_reb_hit += a12; n_hit += 1; }
+        prev = cur;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (st != MD_OK) return st;
+    out[0] = t_step / n_steps;
+    out[1] = t_reb / n_steps;
+    out[2] = n_hit > 0 ? t_reb_hit / n_hit : 0.0;
+    out[3] = n_hit;
+    out[4] = t_tot;
     return MD_OK;
 }
 
@@ -1282,7 +1356,9 @@ md_status md_debug_neighbours(md_system *s, int32_t slot, int32_t *counts, int32
     std::vector<int> cnt(n), lst((size_t)n * lc);
     std::vector<int4> mt(n);
     HIPCHK(s, hipMemcpyAsync(cnt.data(), s->nbr_cnt + h.off, 4 * n, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipMemcpy2DAsync(lst.data(), 4 * n, s->nbr + h.off, 4 * P, 4 * n, lc, hipMemcpyDeviceToHost, s->stream));
+    // blocked layout: entry k of slot i at int4 row k/4, lane k%4
+    HIPCHK(s, hipMemcpy2DAsync(lst.data(), 16 * n, s->nbr + 4 * h.off, 16 * P, 16 * n, lc / 4,
+                               hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipMemcpyAsync(mt.data(), s->meta + h.off, 16 * n, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     for (int64_t k = 0; k < n; ++k) {
@@ -1292,7 +1368,7 @@ md_status md_debug_neighbours(md_system *s, int32_t slot, int32_t *counts, int32
         for (int q = 0; q < cap; ++q) {
             int v = -1;
             if (q < cnt[k] && q < lc) {
-                int j = lst[(size_t)q * n + k] - (int)h.off;
+                int j = lst[(size_t)(q >> 2) * 4 * n + 4 * k + (q & 3)] - (int)h.off;
                 v = (j >= 0 && j < n) ? mt[j].w : -2;
             }
             ids[(size_t)id * cap + q] = v;

@@ -251,42 +251,100 @@ __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, con
     return c;
 }
 
-// Force (and optionally energy/virial) on particle i from its list, fixed-
-// point snapshots, FP32 pair term.  Returns the accumulated force.
-template <int P, bool EN>
+// The Verlet list of particle i is stored in blocks of four entries:
+// entry k lives in int4 row k/4, lane k%4, of column i (nbr4[(k/4)*P + i]),
+// so one dwordx4 load fetches four indices and a wave reads 1 KB contiguous.
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 list_row(const KArena &A, int i, int q)
+{
+    const v4i *p = (const v4i *)A.nbr + (size_t)q * A.P + i;
+    v4i v = __builtin_nontemporal_load(p); // streamed once per step: keep it out of the caches
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
+// One list entry, fixed-point snapshots, FP32 pair term.  With a uniform
+// cutoff ratio (rc_ab = c sigma_ab for every pair) the cutoff test is
+// sigma^2/r^2 > 1/c^2 and needs no per-pair cutoff.
+template <int P, bool EN, bool UNI>
+__device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts &c, const PairDev &pp,
+                                            int si, FAcc<P> &acc, double &e_sum, double &w_sum)
+{
+    const int ix = (int)(xi.x - xj.x), iy = (int)(xi.y - xj.y), iz = (int)(xi.z - xj.z);
+    const float dx = (float)ix, dy = (float)iy, dz = (float)iz;
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const bool b = (xj.w & SPECIES_MASK) != 0;
+    const float sig2 = b ? c.sig2s[1] : c.sig2s[0];
+    const float e24 = b ? c.e24s[1] : c.e24s[0];
+    const float ir2 = __builtin_amdgcn_rcpf(r2);
+    const float s2 = sig2 * ir2;
+    const float s6 = s2 * s2 * s2;
+    const float t = __builtin_fmaf(2.0f, s6, -1.0f);
+    float fs = e24 * ir2 * s6 * t;
+    bool in;
+    if (UNI) in = s2 > pp.s2cut;
+    else in = r2 < (b ? c.rc2s[1] : c.rc2s[0]);
+    fs = in ? fs : 0.0f;
+    acc.add(fs, dx, dy, dz, ix, iy, iz);
+    if (EN) {
+        const int tt = si * 2 + (b ? 1 : 0);
+        if (in) {
+            e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
+            w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
+        }
+    }
+}
+
+// Snapshot gather with a 32-bit byte offset from a uniform base.
+__device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int j)
+{
+    return *(const uint4 *)((const char *)snap + (uint32_t)j * 16u);
+}
+
+// Force (and optionally energy/virial) on particle i from its list.  The
+// loop is software-pipelined over blocks of four entries with two register
+// buffers: while one block is computed, the snapshots of the next block and
+// the indices of the block after it are in flight.  Lists are padded to a
+// multiple of eight valid entries by the list build and row indices are clamped, so every
+// prefetch is unconditional and no control-flow join forces the memory
+// counters to drain inside the loop.
+template <int P, bool EN, bool UNI>
 __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
                                             uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
                                             FAcc<P> &acc, double &e_sum, double &w_sum)
 {
-    const int *__restrict__ lp = A.nbr + i;
     const int cnt = A.nbr_cnt[i];
-    const size_t P_ = (size_t)A.P;
+    const int nq = ((cnt + 7) >> 3) << 1; // blocks of four, padded to an even count
     acc.init();
-    for (int k = 0; k < cnt; ++k) {
-        int j = __builtin_nontemporal_load(lp + (size_t)k * P_);
-        uint4 xj = snap[j];
-        int ix = (int)(xi.x - xj.x), iy = (int)(xi.y - xj.y), iz = (int)(xi.z - xj.z);
-        float dx = (float)ix, dy = (float)iy, dz = (float)iz;
-        float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        bool b = (xj.w & SPECIES_MASK) != 0;
-        float rc2 = b ? c.rc2s[1] : c.rc2s[0];
-        float sig2 = b ? c.sig2s[1] : c.sig2s[0];
-        float e24 = b ? c.e24s[1] : c.e24s[0];
-        float ir2 = __builtin_amdgcn_rcpf(r2);
-        float s2 = sig2 * ir2;
-        float s6 = s2 * s2 * s2;
-        float t = __builtin_fmaf(2.0f, s6, -1.0f);
-        float fs = e24 * ir2 * s6 * t;
-        bool in = r2 < rc2;
-        fs = in ? fs : 0.0f;
-        acc.add(fs, dx, dy, dz, ix, iy, iz);
-        if (EN) {
-            int tt = si * 2 + (b ? 1 : 0);
-            if (in) {
-                e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
-                w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
-            }
-        }
+    if (nq == 0) return;
+    const int last = nq - 1;
+    // indices two blocks ahead, snapshots one block ahead
+    int4 ja = list_row(A, i, 0), jb = list_row(A, i, 1);
+    uint4 a0 = ld_snap(snap, ja.x), a1 = ld_snap(snap, ja.y), a2 = ld_snap(snap, ja.z),
+          a3 = ld_snap(snap, ja.w);
+    ja = list_row(A, i, min(2, last));
+    for (int q = 0; q < nq; q += 2) {
+        // (the scheduling barriers keep each batch of loads ahead of the
+        // block computed while it is in flight)
+        const uint4 b0 = ld_snap(snap, jb.x), b1 = ld_snap(snap, jb.y), b2 = ld_snap(snap, jb.z),
+                    b3 = ld_snap(snap, jb.w);
+        jb = list_row(A, i, min(q + 3, last));
+        __builtin_amdgcn_sched_barrier(0);
+        entry_fixed<P, EN, UNI>(xi, a0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, a1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, a2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, a3, c, pp, si, acc, e_sum, w_sum);
+        __builtin_amdgcn_sched_barrier(0);
+        a0 = ld_snap(snap, ja.x);
+        a1 = ld_snap(snap, ja.y);
+        a2 = ld_snap(snap, ja.z);
+        a3 = ld_snap(snap, ja.w);
+        ja = list_row(A, i, min(q + 4, last));
+        __builtin_amdgcn_sched_barrier(0);
+        entry_fixed<P, EN, UNI>(xi, b0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, b1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, b2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, b3, c, pp, si, acc, e_sum, w_sum);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -296,7 +354,6 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
                                           const PairDev &pp, double &fx, double &fy, double &fz,
                                           bool en, double &e_sum, double &w_sum)
 {
-    const int *__restrict__ lp = A.nbr + i;
     const int cnt = A.nbr_cnt[i];
     const size_t P_ = (size_t)A.P;
     const uint4 *__restrict__ snap1 = snap + P_;
@@ -305,30 +362,36 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
     rc2[0] = pp.rc2d[si * 2]; rc2[1] = pp.rc2d[si * 2 + 1];
     sig2[0] = pp.sig2d[si * 2]; sig2[1] = pp.sig2d[si * 2 + 1];
     e24[0] = pp.eps24d[si * 2]; e24[1] = pp.eps24d[si * 2 + 1];
-    for (int k = 0; k < cnt; ++k) {
-        int j = __builtin_nontemporal_load(lp + (size_t)k * P_);
-        double xj, yj, zj, wj;
-        u4_to_dbl2(snap[j], xj, yj);
-        u4_to_dbl2(snap1[j], zj, wj);
-        double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-        dx -= r.L * rint(dx * r.invL);
-        dy -= r.L * rint(dy * r.invL);
-        dz -= r.L * rint(dz * r.invL);
-        double r2 = dx * dx + dy * dy + dz * dz;
-        int b = meta_of_bits(wj) & 1;
-        double ir2 = 1.0 / r2;
-        double s2 = sig2[b] * ir2;
-        double s6 = s2 * s2 * s2;
-        double ff = e24[b] * ir2 * s6 * (2.0 * s6 - 1.0);
-        bool in = r2 < rc2[b];
-        ff = in ? ff : 0.0;
-        fx += ff * dx;
-        fy += ff * dy;
-        fz += ff * dz;
-        if (en && in) {
-            int tt = si * 2 + b;
-            e_sum += 0.5 * (pp.eps4d[tt] * s6 * (s6 - 1.0) - pp.shiftd[tt]);
-            w_sum += 0.5 * ff * r2;
+    const int nq = ((cnt + 7) >> 3) << 1;
+    for (int q = 0; q < nq; ++q) {
+        const int4 jj = list_row(A, i, q);
+        const int js[4] = {jj.x, jj.y, jj.z, jj.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = js[u]; // padding entries lie beyond the cutoff
+            double xj, yj, zj, wj;
+            u4_to_dbl2(snap[j], xj, yj);
+            u4_to_dbl2(snap1[j], zj, wj);
+            double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            dx -= r.L * rint(dx * r.invL);
+            dy -= r.L * rint(dy * r.invL);
+            dz -= r.L * rint(dz * r.invL);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            int b = meta_of_bits(wj) & 1;
+            double ir2 = 1.0 / r2;
+            double s2 = sig2[b] * ir2;
+            double s6 = s2 * s2 * s2;
+            double ff = e24[b] * ir2 * s6 * (2.0 * s6 - 1.0);
+            bool in = r2 < rc2[b];
+            ff = in ? ff : 0.0;
+            fx += ff * dx;
+            fy += ff * dy;
+            fz += ff * dz;
+            if (en && in) {
+                int tt = si * 2 + b;
+                e_sum += 0.5 * (pp.eps4d[tt] * s6 * (s6 - 1.0) - pp.shiftd[tt]);
+                w_sum += 0.5 * ff * r2;
+            }
         }
     }
 }
@@ -336,7 +399,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
 // ------------------------------------------------------------ k_step
 enum { M_ADV = 0, M_FIN = 1, M_IDLE = 2 };
 
-template <int P, bool OBS>
+template <int P, bool OBS, bool UNI>
 __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
 {
     const KArena &A = a.A;
@@ -413,7 +476,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     } else {
         const LaneConsts c = lane_consts(a.pp, si, rp);
         FAcc<P> acc;
-        force_fixed<P, OBS>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum);
+        force_fixed<P, OBS, UNI>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum);
         if (OBS) {
             acc.get(fxd, fyd, fzd);
             double *o = a.obs + (size_t)i * 8;
@@ -508,7 +571,8 @@ __global__ void k_count(const CountArgs a)
 }
 
 // ------------------------------------------------------------ k_scan
-// One workgroup (1024 threads) per slot: exclusive scan of cell counts.
+// One workgroup (1024 threads) per slot: exclusive scan of the cell counts
+// in tiles of 8 cells per thread, cell starts written as absolute slots.
 __global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
 {
     const int s = blockIdx.x;
@@ -516,37 +580,51 @@ __global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
     if (!slot_selected(s, a.force_slot, a.need, a.ctl)) return;
     const RepDev rp = a.rep[s];
     const int ncell = rp.nd * rp.nd * rp.nd;
-    const int T = blockDim.x, t = threadIdx.x;
-    const int per = (ncell + T - 1) / T;
-    const int c0 = min(t * per, ncell), c1 = min(c0 + per, ncell);
+    const int B = blockDim.x, t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6, nw = (B + 63) >> 6;
     const int *cnt = a.count + rp.coff;
-    int local = 0;
-    for (int c = c0; c < c1; ++c) local += cnt[c];
-    // block exclusive scan of `local`
-    __shared__ int wsum[16];
-    const int lane = t & 63, wv = t >> 6;
-    int incl = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    if (t == 0) {
-        int acc = 0;
-        for (int k = 0; k < (T + 63) / 64; ++k) { int v = wsum[k]; wsum[k] = acc; acc += v; }
-    }
-    __syncthreads();
-    int base = rp.off + wsum[wv] + incl - local;
     int *out = a.cs_new + rp.coff;
-    for (int c = c0; c < c1; ++c) { out[c] = base; base += cnt[c]; }
-    if (c1 == ncell && c0 < c1) {
-        out[ncell] = base;
-        if (base != rp.off + rp.n) atomicOr(a.status + s, 4 | 2);
+    __shared__ int wsum[16];
+    __shared__ int tile_total;
+    int carry = 0;
+    for (int base = 0; base < ncell; base += 8 * B) {
+        int v[8];
+        int local = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = base + 8 * t + u;
+            v[u] = c < ncell ? cnt[c] : 0;
+            local += v[u];
+        }
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int w = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += w;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        if (t == 0) {
+            int acc = 0;
+            for (int k = 0; k < nw; ++k) { const int w = wsum[k]; wsum[k] = acc; acc += w; }
+            tile_total = acc;
+        }
+        __syncthreads();
+        int run = rp.off + carry + wsum[wv] + incl - local;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = base + 8 * t + u;
+            if (c < ncell) out[c] = run;
+            run += v[u];
+        }
+        carry += tile_total;
+        __syncthreads();
     }
-    if (ncell == 0 && t == 0) out[0] = rp.off;
-    if (t == 0) a.nreb[s] += 1;
+    if (t == 0) {
+        out[ncell] = rp.off + carry;
+        if (carry != rp.n) atomicOr(a.status + s, 4 | 2);
+        a.nreb[s] += 1;
+    }
 }
 
 // ------------------------------------------------------------ k_permute
@@ -612,12 +690,26 @@ __device__ __forceinline__ void fold_and_copy(const PermArgs &a, const RepDev &r
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_permute(const PermArgs a)
+__device__ __forceinline__ bool in_cell(const PermArgs &a, const RepDev &rp, int q, int c)
 {
     constexpr int NS = Traits<P>::NS;
+    if (NS == 2) {
+        double x, y, z, w;
+        u4_to_dbl2(a.snap[q], x, y);
+        u4_to_dbl2(a.snap[(size_t)a.A.P + q], z, w);
+        return dbl_cell(x, y, z, rp.L, rp.invL, rp.nd) == c;
+    }
+    const uint4 X = a.snap[q];
+    return fixed_cell(X.x, X.y, X.z, rp.nd) == c;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_permute(const PermArgs a)
+{
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6;
+    __shared__ int pref[4][28], pst[4][27];
     const int total = a.items_pref[a.max_slots];
     for (int item = blockIdx.x * wpb + wv; item < total; item += gridDim.x * wpb) {
         const int s = find_item_slot(a.items_pref, a.max_slots, item);
@@ -625,79 +717,99 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
         const RepDev rp = a.rep[s];
         const int c = item - a.items_pref[s];
         const int nd = rp.nd;
-        int ox[3], oy[3], oz[3], nx3;
-        if (nd == 1) {
-            ox[0] = oy[0] = oz[0] = 0;
-            nx3 = 1;
-        } else {
+        const int *cs = a.cs + rp.coff;
+        const int dst0 = a.cs_new[rp.coff + c];
+        const int want = a.cs_new[rp.coff + c + 1] - dst0;
+        // the old cells that can hold members of new cell c, ascending (so
+        // that the flattened candidates are in old slot order)
+        int nold = 1;
+        if (lane == 0) { pst[wv][0] = cs[0]; pref[wv][0] = 0; pref[wv][1] = cs[1] - cs[0]; }
+        if (nd > 1) {
+            nold = 27;
             const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
             int v[3][3] = {{(cx + nd - 1) % nd, cx, (cx + 1) % nd},
                            {(cy + nd - 1) % nd, cy, (cy + 1) % nd},
                            {(cz + nd - 1) % nd, cz, (cz + 1) % nd}};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) { // sort three values ascending
+            for (int d = 0; d < 3; ++d) {
                 int *u = v[d];
                 if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
                 if (u[1] > u[2]) { int t = u[1]; u[1] = u[2]; u[2] = t; }
                 if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
             }
-            for (int k = 0; k < 3; ++k) { ox[k] = v[0][k]; oy[k] = v[1][k]; oz[k] = v[2][k]; }
-            nx3 = 3;
+            int len = 0, st0 = 0;
+            if (lane < 27) {
+                const int kx = lane % 3, ky = (lane / 3) % 3, kz = lane / 9;
+                const int oc = v[0][kx] + nd * (v[1][ky] + nd * v[2][kz]);
+                st0 = cs[oc];
+                len = cs[oc + 1] - st0;
+            }
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
+            }
+            if (lane < 27) { pst[wv][lane] = st0; pref[wv][lane + 1] = incl; }
+            if (lane == 0) pref[wv][0] = 0;
         }
-        const int *cs = a.cs + rp.coff;
-        const int dst0 = a.cs_new[rp.coff + c];
+        __builtin_amdgcn_wave_barrier();
+        const int tot = pref[wv][nold];
         int run = 0;
-        for (int kz = 0; kz < nx3; ++kz)
-            for (int ky = 0; ky < nx3; ++ky)
-                for (int kx = 0; kx < nx3; ++kx) {
-                    const int oc = ox[kx] + nd * (oy[ky] + nd * oz[kz]);
-                    const int q0 = cs[oc], q1 = cs[oc + 1];
-                    for (int qb = q0; qb < q1; qb += 64) {
-                        const int q = qb + lane;
-                        bool match = false;
-                        if (q < q1) {
-                            if (nd == 1) match = true;
-                            else if (NS == 2) {
-                                double x, y, z, w;
-                                u4_to_dbl2(a.snap[q], x, y);
-                                u4_to_dbl2(a.snap[(size_t)a.A.P + q], z, w);
-                                match = dbl_cell(x, y, z, rp.L, rp.invL, nd) == c;
-                            } else {
-                                uint4 X = a.snap[q];
-                                match = fixed_cell(X.x, X.y, X.z, nd) == c;
-                            }
-                        }
-                        unsigned long long bal = __ballot(match);
-                        if (match) {
-                            int rank = run + __popcll(bal & ((1ull << lane) - 1ull));
-                            fold_and_copy<P>(a, rp, q, dst0 + rank);
-                        }
-                        run += __popcll(bal);
-                    }
+        for (int b = 0; b < tot; b += 256) {
+            int q[4];
+            bool m[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = b + 64 * u + lane;
+                q[u] = -1;
+                if (e < tot) {
+                    int r = 0;
+                    while (r + 1 < nold && pref[wv][r + 1] <= e) ++r;
+                    q[u] = pst[wv][r] + (e - pref[wv][r]);
                 }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) m[u] = q[u] >= 0 && (nd == 1 || in_cell<P>(a, rp, q[u], c));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned long long bal = __ballot(m[u]);
+                if (m[u]) fold_and_copy<P>(a, rp, q[u], dst0 + run + __popcll(bal & ((1ull << lane) - 1ull)));
+                run += __popcll(bal);
+            }
+        }
         // every particle counted in this cell must have come from a
         // neighbouring old cell; a shortfall means a particle jumped further
-        if (lane == 0 && run != a.cs_new[rp.coff + c + 1] - dst0) atomicOr(a.status + s, 4);
+        if (lane == 0 && run != want) atomicOr(a.status + s, 4);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 // ------------------------------------------------------------ k_build
-// One workgroup per row segment of cells: stage the neighbourhood in LDS,
-// build the canonical-order list of every member.
-#define BUILD_LDS_CAP 3072   // staged candidates (x 16 B = 48 KB, fixed point)
-#define BUILD_MAX_NX 18      // cells per staged row (width + 2 halo)
+// One workgroup per row segment of cells (cells x0..x1-1 of row (y, z)):
+// the 9 neighbouring rows over x0-1..x1 are staged in LDS, then every member
+// writes its list in the canonical order.
+#define BUILD_LDS_CAP 3072 // staged candidates (x 16 B = 48 KB, fixed point)
+#define BUILD_MAX_NX 18    // cells per staged row (width + 2 halo)
+#define BUILD_TAB (9 * BUILD_MAX_NX)
+
+struct BuildTabs {
+    int start[BUILD_TAB]; // LDS start of staged cell (global start when not staged)
+    int cnt[BUILD_TAB];
+    int glob[BUILD_TAB];  // global start of the cell
+    int run_lds[19], run_glob[19];
+    int nruns, total, fits, NX;
+};
 
 template <int P, bool FROM_LDS>
-__device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &rp, int i,
-                                             int lx_m, const int (*tstart)[BUILD_MAX_NX],
-                                             const int (*tcnt)[BUILD_MAX_NX],
-                                             const int (*tglob)[BUILD_MAX_NX], int NX, bool full,
-                                             const uint4 *cand, int s, int nd)
+__device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
+                                             const BuildTabs &T, bool full, const uint4 *cand, int s,
+                                             int nd)
 {
     constexpr int NS = Traits<P>::NS;
     const KArena &A = a.A;
     const size_t P_ = (size_t)A.P;
-    // member data
+    const int NX = T.NX;
     uint4 xi = a.src_x[i];
     double xd = 0, yd = 0, zd = 0, wd = 0;
     uint32_t meta;
@@ -707,71 +819,95 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         meta = meta_of_bits(wd);
     } else meta = xi.w;
     const int si = (int)(meta & SPECIES_MASK);
-    float rl2s[2];
-    double rl2d[2];
+    float rl2s0, rl2s1;
+    double rl2d0 = a.pp.rl2d[si * 2], rl2d1 = a.pp.rl2d[si * 2 + 1];
     {
-        double u = (double)rp.sc;
-        rl2s[0] = (float)(a.pp.rl2d[si * 2] / (u * u));
-        rl2s[1] = (float)(a.pp.rl2d[si * 2 + 1] / (u * u));
-        rl2d[0] = a.pp.rl2d[si * 2];
-        rl2d[1] = a.pp.rl2d[si * 2 + 1];
+        const double u = (double)rp.sc;
+        rl2s0 = (float)(rl2d0 / (u * u));
+        rl2s1 = (float)(rl2d1 / (u * u));
     }
+    const int cap4 = A.cap >> 2;
+    int4 *rows = (int4 *)A.nbr_w + i;
+    int4 buf = make_int4(0, 0, 0, 0);
     int cnt = 0;
-    int *col = A.nbr_w + i;
-    const int cap = A.cap;
-    auto scan_cell = [&](int row, int lx) {
-        const int st = tstart[row][lx], n = tcnt[row][lx], g0 = tglob[row][lx];
-        for (int k = 0; k < n; ++k) {
+    int pad = -1; // first candidate outside the list radius
+    auto scan_cell = [&](int k) {
+        const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+        for (int e = 0; e < n; ++e) {
             bool acc;
             if (NS == 2) {
                 double xj, yj, zj, wj;
                 if (FROM_LDS) {
-                    u4_to_dbl2(cand[2 * (st + k)], xj, yj);
-                    u4_to_dbl2(cand[2 * (st + k) + 1], zj, wj);
+                    u4_to_dbl2(cand[2 * (st + e)], xj, yj);
+                    u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
                 } else {
-                    u4_to_dbl2(a.src_x[st + k], xj, yj);
-                    u4_to_dbl2(a.src_x[P_ + st + k], zj, wj);
+                    u4_to_dbl2(a.src_x[st + e], xj, yj);
+                    u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
                 }
                 double dx = xd - xj, dy = yd - yj, dz = zd - zj;
                 dx -= rp.L * rint(dx * rp.invL);
                 dy -= rp.L * rint(dy * rp.invL);
                 dz -= rp.L * rint(dz * rp.invL);
-                double r2 = dx * dx + dy * dy + dz * dz;
-                int b = meta_of_bits(wj) & 1;
-                acc = r2 < rl2d[b];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                acc = r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
             } else {
-                uint4 xj = FROM_LDS ? cand[st + k] : a.src_x[st + k];
-                float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
-                      dz = (float)(int)(xi.z - xj.z);
-                float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                acc = r2 < rl2s[(xj.w & SPECIES_MASK) ? 1 : 0];
+                const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+                const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
+                            dz = (float)(int)(xi.z - xj.z);
+                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                acc = r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
             }
-            const int j = g0 + k;
+            const int j = g0 + e;
+            pad = (!acc && pad < 0) ? j : pad;
             if (acc && j != i) {
-                if (cnt < cap) col[(size_t)cnt * P_] = j;
+                const int r = cnt & 3;
+                buf.x = r == 0 ? j : buf.x;
+                buf.y = r == 1 ? j : buf.y;
+                buf.z = r == 2 ? j : buf.z;
+                buf.w = r == 3 ? j : buf.w;
+                if (r == 3 && (cnt >> 2) < cap4) rows[(size_t)(cnt >> 2) * P_] = buf;
                 ++cnt;
             }
         }
     };
     if (nd == 1) {
-        scan_cell(0, 0);
+        scan_cell(0);
     } else {
-        // own cell first, then each half-space offset and its opposite
-        scan_cell(4, lx_m);
-#pragma unroll 1
+        // own cell, then each half-space offset o followed by -o
+        constexpr int H[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0}, {-1, -1, 1},
+                                  {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1}, {1, 0, 1},
+                                  {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+        auto visit = [&](int dx, int dy, int dz) {
+            int lx = lx_m + dx;
+            if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
+            scan_cell(((dz + 1) * 3 + (dy + 1)) * NX + lx);
+        };
+        visit(0, 0, 0);
+#pragma unroll
         for (int k = 0; k < 13; ++k) {
-            int dx, dy, dz;
-            half_offset(k, dx, dy, dz);
-            for (int sgn = 1; sgn >= -1; sgn -= 2) {
-                int ddx = sgn * dx, ddy = sgn * dy, ddz = sgn * dz;
-                int row = (ddz + 1) * 3 + (ddy + 1);
-                int lx = full ? (lx_m + ddx + nd) % nd : lx_m + ddx;
-                scan_cell(row, lx);
-            }
+            visit(H[k][0], H[k][1], H[k][2]);
+            visit(-H[k][0], -H[k][1], -H[k][2]);
         }
     }
-    A.nbr_cnt_w[i] = cnt < cap ? cnt : cap;
-    if (cnt > cap) atomicOr(a.status + s, 1);
+    // Pad the last block of four with a particle that was outside the list
+    // radius at this build: it stays beyond the force cutoff until the next
+    // build (each particle moves at most skin/2), so the force loop needs no
+    // per-entry validity test.
+    // Lists are padded to a multiple of 8 entries (two blocks of four).
+    if (cnt & 7) {
+        if (cnt & 3) {
+            const int r = cnt & 3;
+            buf.y = r <= 1 ? pad : buf.y;
+            buf.z = r <= 2 ? pad : buf.z;
+            buf.w = pad;
+            if ((cnt >> 2) < cap4) rows[(size_t)(cnt >> 2) * P_] = buf;
+        }
+        const int q = (cnt + 3) >> 2; // first untouched block
+        if ((q & 1) && q < cap4) rows[(size_t)q * P_] = make_int4(pad, pad, pad, pad);
+        if (pad < 0) atomicOr(a.status + s, 8);
+    }
+    A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
+    if (cnt > A.cap) atomicOr(a.status + s, 1);
 }
 
 template <int P>
@@ -797,93 +933,122 @@ template <int P>
 __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
 {
     constexpr int NS = Traits<P>::NS;
-    __shared__ int tstart[9][BUILD_MAX_NX], tcnt[9][BUILD_MAX_NX], tglob[9][BUILD_MAX_NX];
-    __shared__ int sfits;
+    __shared__ BuildTabs T;
     extern __shared__ uint4 cand[];
-    const int total = a.items_pref[a.max_slots];
-    const int T = blockDim.x, t = threadIdx.x;
-    const int cap_cand = a.lds_cap;
-    for (int it = remap_block(blockIdx.x, gridDim.x, a.xcd); it < total; it += gridDim.x) {
+    const int total_items = a.items_pref[a.max_slots];
+    const int B = blockDim.x, t = threadIdx.x;
+    for (int it = remap_block(blockIdx.x, gridDim.x, a.xcd); it < total_items; it += gridDim.x) {
         const int s = find_item_slot(a.items_pref, a.max_slots, it);
         if (!slot_selected(s, a.force_slot, a.need, a.ctl)) continue;
         const RepDev rp = a.rep[s];
         const int nd = rp.nd;
         const int item = it - a.items_pref[s];
         const int *cs = a.cs_new + rp.coff;
-        int m0, m1, NX = 1, x0 = 0, cy = 0, cz = 0;
+        int m0, m1, NX = 1, x0 = 0, x1 = 1, rowbase = 0;
         bool full = true;
         if (nd == 1) {
-            m0 = rp.off + item * T;
-            m1 = min(m0 + T, rp.off + rp.n);
+            m0 = rp.off + item * B;
+            m1 = min(m0 + B, rp.off + rp.n);
             if (t == 0) {
-                tstart[0][0] = rp.off; tcnt[0][0] = rp.n; tglob[0][0] = rp.off;
+                T.glob[0] = rp.off;
+                T.cnt[0] = rp.n;
+                T.start[0] = 0;
+                T.run_lds[0] = 0; T.run_glob[0] = rp.off; T.run_lds[1] = rp.n;
+                T.nruns = 1;
+                T.total = rp.n;
+                T.fits = rp.n <= a.lds_cap;
+                if (!T.fits) T.start[0] = rp.off;
+                T.NX = 1;
                 if (item == 0 && a.from_scratch) { a.cs[rp.coff] = cs[0]; a.cs[rp.coff + 1] = cs[1]; }
             }
         } else {
             const int W = a.width;
-            const int nseg = (nd <= W + 2) ? 1 : (nd + W - 1) / W;
-            const int seg = item % nseg, row = item / nseg;
-            cy = row % nd; cz = row / nd;
             full = nd <= W + 2;
-            x0 = full ? 0 : seg * W;
-            const int xw = full ? nd : min(W, nd - x0);
-            NX = full ? nd : xw + 2;
-            const int rowbase = nd * (cy + nd * cz);
+            const int nseg = full ? 1 : (nd + W - 1) / W;
+            const int seg = item % nseg, row = item / nseg;
+            const int cy = row % nd, cz = row / nd;
+            x0 = full ? 0 : (seg * nd) / nseg;           // balanced segments
+            x1 = full ? nd : ((seg + 1) * nd) / nseg;
+            NX = full ? nd : x1 - x0 + 2;
+            rowbase = nd * (cy + nd * cz);
             m0 = cs[rowbase + x0];
-            m1 = cs[rowbase + x0 + xw];
-            if (a.from_scratch) // retire the old cell starts of this segment
-                for (int k = t; k < xw; k += T) {
-                    a.cs[rp.coff + rowbase + x0 + k] = cs[rowbase + x0 + k];
-                    if (rowbase + x0 + k == nd * nd * nd - 1)
-                        a.cs[rp.coff + nd * nd * nd] = cs[nd * nd * nd];
-                }
-            for (int k = t; k < 9 * NX; k += T) {
-                int rw = k / NX, lx = k % NX;
-                int dz = rw / 3 - 1, dy = rw % 3 - 1;
-                int gx = full ? lx : (x0 - 1 + lx + nd) % nd;
-                int gy = (cy + dy + nd) % nd, gz = (cz + dz + nd) % nd;
-                int cc = gx + nd * (gy + nd * gz);
-                tglob[rw][lx] = cs[cc];
-                tcnt[rw][lx] = cs[cc + 1] - cs[cc];
+            m1 = cs[rowbase + x1];
+            if (a.from_scratch) { // retire the old cell starts of this segment
+                for (int k = x0 + t; k < x1; k += B) a.cs[rp.coff + rowbase + k] = cs[rowbase + k];
+                if (t == 0 && rowbase + x1 == nd * nd * nd)
+                    a.cs[rp.coff + nd * nd * nd] = cs[nd * nd * nd];
             }
-        }
-        __syncthreads();
-        if (t == 0) { // LDS offsets of the staged cells
-            int acc = 0;
-            for (int rw = 0; rw < (nd == 1 ? 1 : 9); ++rw)
-                for (int lx = 0; lx < NX; ++lx) { tstart[rw][lx] = acc; acc += tcnt[rw][lx]; }
-            sfits = acc <= cap_cand;
-            if (!sfits) // fall back to global reads: start = global index
-                for (int rw = 0; rw < (nd == 1 ? 1 : 9); ++rw)
-                    for (int lx = 0; lx < NX; ++lx) tstart[rw][lx] = tglob[rw][lx];
-        }
-        __syncthreads();
-        const bool fits = sfits != 0;
-        if (fits) { // stage: each cell's particles are contiguous in the arena
-            const int nrow = nd == 1 ? 1 : 9;
-            for (int rw = 0; rw < nrow; ++rw)
-                for (int lx = 0; lx < NX; ++lx) {
-                    const int g0 = tglob[rw][lx], n = tcnt[rw][lx], l0 = tstart[rw][lx];
-                    for (int k = t; k < n; k += T) {
-                        if (NS == 2) {
-                            cand[2 * (l0 + k)] = a.src_x[g0 + k];
-                            cand[2 * (l0 + k) + 1] = a.src_x[(size_t)a.A.P + g0 + k];
-                        } else cand[l0 + k] = a.src_x[g0 + k];
+            const int gs = full ? 0 : (x0 - 1 + nd) % nd; // first staged x
+            for (int k = t; k < 9 * NX; k += B) {
+                const int rw = k / NX, lx = k - rw * NX;
+                const int dz = rw / 3 - 1, dy = rw % 3 - 1;
+                int gx = gs + lx;
+                gx -= gx >= nd ? nd : 0;
+                int gy = cy + dy, gz = cz + dz;
+                gy += gy < 0 ? nd : 0; gy -= gy >= nd ? nd : 0;
+                gz += gz < 0 ? nd : 0; gz -= gz >= nd ? nd : 0;
+                const int cc = gx + nd * (gy + nd * gz);
+                T.glob[k] = cs[cc];
+                T.cnt[k] = cs[cc + 1] - cs[cc];
+            }
+            if (t == 0) T.NX = NX;
+            __syncthreads();
+            if (t < 64) { // exclusive scan of the staged cell sizes (one wave)
+                const int ncells = 9 * NX;
+                int carry = 0;
+                for (int b = 0; b < ncells; b += 64) {
+                    const int k = b + t;
+                    const int v = k < ncells ? T.cnt[k] : 0;
+                    int incl = v;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int u = __shfl_up(incl, o, 64);
+                        if (t >= o) incl += u;
                     }
+                    if (k < ncells) T.start[k] = carry + incl - v;
+                    carry += __shfl(incl, 63, 64);
                 }
+                if (t == 0) { T.total = carry; T.fits = carry <= a.lds_cap; }
+            }
+            __syncthreads();
+            if (t < 9) { // contiguous global runs of each staged row (<= 2 with wrap)
+                const int lenA = full ? NX : min(NX, nd - gs);
+                const int k0 = t * NX;
+                T.run_lds[2 * t] = T.start[k0];
+                T.run_glob[2 * t] = T.glob[k0];
+                T.run_lds[2 * t + 1] = lenA < NX ? T.start[k0 + lenA] : T.start[k0 + NX - 1] + T.cnt[k0 + NX - 1];
+                T.run_glob[2 * t + 1] = lenA < NX ? T.glob[k0 + lenA] : T.glob[k0 + NX - 1] + T.cnt[k0 + NX - 1];
+                if (t == 8) { T.run_lds[18] = T.total; T.nruns = 18; }
+            }
+            __syncthreads();
+            if (!T.fits) // candidates are read from the arena: start = global index
+                for (int k = t; k < 9 * NX; k += B) T.start[k] = T.glob[k];
         }
         __syncthreads();
-        for (int i = m0 + t; i < m1; i += T) {
-            int lx_m = 0;
-            if (nd > 1) { // the member's cell is the own-row cell whose range holds i
-                int gx = full ? 0 : x0;
-                const int xe = full ? nd - 1 : min(x0 + a.width, nd) - 1;
-                const int rowbase = nd * (cy + nd * cz);
-                while (gx < xe && cs[rowbase + gx + 1] <= i) ++gx;
-                lx_m = full ? gx : gx - x0 + 1;
+        const bool fits = T.fits != 0;
+        if (fits) { // stage: element e lies in the last run whose LDS start is <= e
+            const int tot = T.total, nr = T.nruns;
+            for (int e = t; e < tot; e += B) {
+                int r = 0;
+                while (r + 1 < nr && T.run_lds[r + 1] <= e) ++r;
+                const int g = T.run_glob[r] + (e - T.run_lds[r]);
+                if (NS == 2) {
+                    cand[2 * e] = a.src_x[g];
+                    cand[2 * e + 1] = a.src_x[(size_t)a.A.P + g];
+                } else cand[e] = a.src_x[g];
             }
-            if (fits) build_member<P, true>(a, rp, i, lx_m, tstart, tcnt, tglob, NX, full, cand, s, nd);
-            else build_member<P, false>(a, rp, i, lx_m, tstart, tcnt, tglob, NX, full, cand, s, nd);
+        }
+        __syncthreads();
+        for (int i = m0 + t; i < m1; i += B) {
+            int lx_m = 0;
+            if (nd > 1) { // the member's cell: own-row staged cell whose range holds i
+                int lx = full ? 0 : 1;
+                const int le = full ? NX - 1 : NX - 2;
+                while (lx < le && T.glob[4 * NX + lx + 1] <= i) ++lx;
+                lx_m = lx;
+            }
+            if (fits) build_member<P, true>(a, rp, i, lx_m, T, full, cand, s, nd);
+            else build_member<P, false>(a, rp, i, lx_m, T, full, cand, s, nd);
             copy_back<P>(a, i);
         }
         __syncthreads();
@@ -891,32 +1056,61 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
 }
 
 // ------------------------------------------------------------ k_obs_reduce
-// Per slot: fixed-order FP64 sums of e_i, w_i, v^2 and v.
+// Deterministic two-pass FP64 sums per slot of e_i, w_i, v^2, v and the list
+// lengths: pass 1 reduces fixed chunks of OBS_CHUNK particles, pass 2 adds
+// the chunk partials of each slot in chunk order.
+#define OBS_CHUNK 4096
+#define OBS_Q 7
+
+__device__ __forceinline__ void block_sum7(double acc[OBS_Q], double (*red)[256])
+{
+    for (int q = 0; q < OBS_Q; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < OBS_Q; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_obs_partial(const ObsArgs a)
+{
+    __shared__ double red[OBS_Q][256];
+    const int total = a.chunk_pref[a.max_slots];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = find_item_slot(a.chunk_pref, a.max_slots, item);
+        const RepDev rp = a.rep[s];
+        const int k0 = (item - a.chunk_pref[s]) * OBS_CHUNK;
+        const int k1 = min(k0 + OBS_CHUNK, rp.n);
+        double acc[OBS_Q] = {0, 0, 0, 0, 0, 0, 0};
+        for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+            const double *o = a.obs + (size_t)(rp.off + k) * 8;
+            acc[0] += o[3];
+            acc[1] += o[4];
+            acc[2] += o[5] * o[5] + o[6] * o[6] + o[7] * o[7];
+            acc[3] += o[5];
+            acc[4] += o[6];
+            acc[5] += o[7];
+            acc[6] += (double)a.nbr_cnt[rp.off + k];
+        }
+        block_sum7(acc, red);
+        if (threadIdx.x < OBS_Q) a.partial[(size_t)item * 8 + threadIdx.x] = red[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
 __global__ void __launch_bounds__(256) k_obs_reduce(const ObsArgs a)
 {
     const int s = blockIdx.x;
     if (s >= a.max_slots || !a.ctl[s].z) return;
-    const RepDev rp = a.rep[s];
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = threadIdx.x; k < rp.n; k += blockDim.x) {
-        const double *o = a.obs + (size_t)(rp.off + k) * 8;
-        acc[0] += o[3];
-        acc[1] += o[4];
-        acc[2] += o[5] * o[5] + o[6] * o[6] + o[7] * o[7];
-        acc[3] += o[5];
-        acc[4] += o[6];
-        acc[5] += o[7];
-    }
-    __shared__ double red[6][256];
-    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 6; ++q) a.out[s * 8 + q] = red[q][0];
+    __shared__ double red[OBS_Q][256];
+    double acc[OBS_Q] = {0, 0, 0, 0, 0, 0, 0};
+    const int c0 = a.chunk_pref[s], c1 = a.chunk_pref[s + 1];
+    // chunk partials of the slot, in chunk order within each thread's stride
+    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x)
+        for (int q = 0; q < OBS_Q; ++q) acc[q] += a.partial[(size_t)c * 8 + q];
+    block_sum7(acc, red);
+    if (threadIdx.x < OBS_Q) a.out[s * 8 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // ------------------------------------------------------------ k_scale_vel
@@ -969,8 +1163,11 @@ template <int P>
 static hipError_t launch_step_t(const StepArgs &a, int block, bool obs, hipStream_t s)
 {
     int grid = (a.A.P + block - 1) / block;
-    if (obs) hipLaunchKernelGGL((k_step<P, true>), dim3(grid), dim3(block), 0, s, a);
-    else hipLaunchKernelGGL((k_step<P, false>), dim3(grid), dim3(block), 0, s, a);
+    const bool uni = a.pp.uniform != 0 && P != PREC_FP64;
+    if (obs && uni) hipLaunchKernelGGL((k_step<P, true, true>), dim3(grid), dim3(block), 0, s, a);
+    else if (obs) hipLaunchKernelGGL((k_step<P, true, false>), dim3(grid), dim3(block), 0, s, a);
+    else if (uni) hipLaunchKernelGGL((k_step<P, false, true>), dim3(grid), dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, false, false>), dim3(grid), dim3(block), 0, s, a);
     LAUNCH_CHECK();
 }
 
@@ -1025,6 +1222,7 @@ hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipSt
 
 hipError_t launch_obs_reduce(const ObsArgs &a, hipStream_t s)
 {
+    hipLaunchKernelGGL(k_obs_partial, dim3(1024), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_obs_reduce, dim3(a.max_slots), dim3(256), 0, s, a);
     LAUNCH_CHECK();
 }

@@ -90,7 +90,10 @@ struct ObsArgs {
     const RepDev *rep;
     const Ctl *ctl;
     const double *obs;
-    double *out; // [max_slots][8]
+    const int *nbr_cnt;
+    const int *chunk_pref; // per slot prefix of ceil(n / 4096) chunks
+    double *partial;       // [chunks][8]
+    double *out;           // [max_slots][8]
 };
 
 struct ScaleArgs {

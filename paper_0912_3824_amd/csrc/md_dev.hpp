@@ -62,6 +62,8 @@ struct PairDev {
     float hs2;       // (skin/2)^2
     double hs2d;
     int nsp;
+    int uniform;     // 1 if rc_ab / sigma_ab is the same for every pair
+    float s2cut;     // then (sigma_ab / rc_ab)^2: a pair is inside iff sigma^2/r^2 > s2cut
 };
 
 // Integration constants (dt and dt/2m) in every representation.

@@ -30,7 +30,7 @@ EXPORTS = [
     "md_workspace_bytes", "md_validate", "md_create", "md_init", "md_destroy",
     "md_attach", "md_detach", "md_rebuild_neighbours", "md_forces", "md_step",
     "md_set_target", "md_advance", "md_poll", "md_observables",
-    "md_scale_velocities", "md_sync", "md_get_state", "md_checkpoint_bytes",
+    "md_scale_velocities", "md_profile_steps", "md_sync", "md_get_state", "md_checkpoint_bytes",
     "md_save", "md_restore", "md_debug_neighbours", "md_get_launch",
     "md_set_launch", "md_ds_eval", "md_strerror", "md_last_error",
     "md_abi_version",
@@ -56,6 +56,7 @@ class MdObs(ctypes.Structure):
                 ("temperature", ctypes.c_double), ("virial", ctypes.c_double),
                 ("pressure", ctypes.c_double), ("momentum", ctypes.c_double * 3),
                 ("step", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64),
+                ("list_entries", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("n", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
@@ -63,6 +64,7 @@ class MdObs(ctypes.Structure):
                 "temperature": self.temperature, "virial": self.virial,
                 "pressure": self.pressure, "momentum": np.array(list(self.momentum)),
                 "step": self.step, "n_rebuilds": self.n_rebuilds,
+                "list_entries": self.list_entries,
                 "status": self.status, "n": self.n}
 
 
@@ -117,6 +119,7 @@ def load():
         "md_observables": (i32, [vp, ctypes.POINTER(MdObs)]),
         "md_scale_velocities": (i32, [vp, i32, ctypes.c_double]),
         "md_sync": (i32, [vp]),
+        "md_profile_steps": (i32, [vp, i64, dp]),
         "md_get_state": (i32, [vp, i32, dp, dp, ip]),
         "md_checkpoint_bytes": (i64, [vp, i32]),
         "md_save": (i32, [vp, i32, vp, i64]),
@@ -301,6 +304,14 @@ class MdSystem:
     def scale_velocities(self, slot: int, factor: float):
         self._check(self.lib.md_scale_velocities(self.h, int(slot), float(factor)),
                     "md_scale_velocities")
+
+    def profile_steps(self, n_steps: int) -> dict:
+        """Eager steps with hipEvent timing of the fused kernel and rebuilds."""
+        out = np.zeros(5)
+        self._check(self.lib.md_profile_steps(self.h, int(n_steps), _dp(out)), "md_profile_steps")
+        return {"step_kernel_ms": out[0], "rebuild_ms_mean": out[1],
+                "rebuild_ms_when_rebuilding": out[2], "rebuild_steps": int(out[3]),
+                "total_ms": out[4]}
 
     def sync(self):
         self._check(self.lib.md_sync(self.h), "md_sync")

@@ -1,0 +1,109 @@
+"""Autotuner of libmdx launch shapes.
+
+The knobs (md_launch: block size of the fused step kernel, cells per LDS row
+segment and block size of the list build, steps per captured hipGraph, XCD-
+aware tile mapping) change no result bit: lists are in a canonical order and
+every particle sums its own list sequentially.  The tuner therefore times
+candidate shapes on the live pool, from a saved checkpoint so that every
+candidate advances the same trajectory, and keeps the fastest.  Results are
+cached in a JSON file keyed by (precision, particle-count bucket, replicas).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+from typing import Dict, List, Optional
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+SPACE = {
+    "step_block": [64, 128, 256, 512],
+    "build_width": [4, 8, 12],
+    "build_block": [128, 256, 512],
+    "graph_steps": [32],
+    "xcd_remap": [0, 1],
+}
+
+
+def bucket(n_total: int) -> int:
+    return int(round(math.log2(max(n_total, 1)) * 2))
+
+
+def key_of(pool) -> str:
+    n = sum(pool.sizes.values())
+    return f"p{pool.cfg.precision}_b{bucket(n)}_r{len(pool.sizes)}"
+
+
+def _time_steps(pool, steps: int) -> float:
+    import torch
+    pool.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pool.step(steps)
+    pool.sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def tune(pool, steps: int = 200, space: Optional[Dict[str, List[int]]] = None,
+         cache: Optional[str] = CACHE, verbose: bool = False) -> dict:
+    """Time every shape in `space` on the live pool and apply the fastest.
+
+    Each candidate starts from the same checkpoint of every attached slot, so
+    the timed steps (including their list rebuilds) are identical work.
+    """
+    space = space or SPACE
+    slots = sorted(pool.sizes)
+    blobs = {s: pool.save(s) for s in slots}
+    sizes = dict(pool.sizes)
+    boxes = dict(pool.boxes)
+
+    def restore_all():
+        for s in slots:
+            pool.detach(s)
+        for s in slots:
+            pool.restore(s, blobs[s], sizes[s], boxes[s])
+
+    results = []
+    names = list(space)
+    for combo in itertools.product(*(space[k] for k in names)):
+        shape = dict(zip(names, combo))
+        restore_all()
+        pool.set_launch(**shape)
+        pool.step(2)          # graph capture / warm caches
+        restore_all()
+        dt = _time_steps(pool, steps)
+        results.append((dt, shape))
+        if verbose:
+            print(f"[tune] {shape} -> {dt * 1e6:.1f} us/step", flush=True)
+    results.sort(key=lambda r: r[0])
+    best = results[0][1]
+    restore_all()
+    pool.set_launch(**best)
+    if cache:
+        try:
+            data = json.load(open(cache)) if os.path.exists(cache) else {}
+        except (OSError, ValueError):
+            data = {}
+        data[key_of(pool)] = {"shape": best, "us_per_step": results[0][0] * 1e6}
+        with open(cache, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+    return {"best": best, "us_per_step": results[0][0] * 1e6,
+            "all": [(r[0] * 1e6, r[1]) for r in results]}
+
+
+def apply_cached(pool, cache: str = CACHE) -> Optional[dict]:
+    """Apply a cached shape for this pool's key, if one exists."""
+    if not os.path.exists(cache):
+        return None
+    try:
+        data = json.load(open(cache))
+    except (OSError, ValueError):
+        return None
+    hit = data.get(key_of(pool))
+    if hit:
+        pool.set_launch(**hit["shape"])
+        return hit["shape"]
+    return None

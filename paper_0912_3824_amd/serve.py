@@ -1,0 +1,155 @@
+"""Continuous-batching serving loop for MD trajectory jobs on one GPU.
+
+A job is a Kob-Andersen replica (N particles, a number of steps).  Jobs
+arrive over time; the loop keeps every running job's state resident in one
+libmdx pool and advances all of them together with md_advance, in chunks of
+graph-captured steps.  Between chunks it
+
+  * retires jobs that reached their step target (md_poll reports the step
+    count and that the velocities are back at a full step), copying their
+    final state out and releasing their slot and arena ranges (md_detach);
+  * admits queued jobs in arrival order while a slot is free and the job's
+    HBM footprint (its particle and cell ranges in the pool's arena) fits
+    (md_attach refuses with MD_E_CAPACITY otherwise; the job then waits).
+
+A replica's trajectory does not depend on the other replicas in the pool,
+so every job's result is bitwise the one it would get alone.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from . import mdx
+
+
+@dataclasses.dataclass
+class JobResult:
+    job_id: int
+    n: int
+    steps: int
+    arrival: float
+    admitted: float
+    finished: float
+    pos: np.ndarray
+    vel: np.ndarray
+    image: np.ndarray
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint_bytes(pool: "mdx.MdSystem", n: int) -> int:
+    """Device bytes a job of n particles occupies in the pool's arena."""
+    per = pool.ws_bytes / max(1, pool.cfg.max_particles)
+    return int(math.ceil(per * n))
+
+
+class Server:
+    """Serve trajectory jobs from a pool of `max_slots` slots whose arena holds
+    `max_particles` particles (chosen from an HBM budget by the caller)."""
+
+    def __init__(self, table, precision="ds", dt=0.001, skin=0.3, max_slots=32,
+                 max_particles=2_000_000, chunk_steps=256, device="cuda:0",
+                 make_system: Optional[Callable] = None):
+        cfg = mdx.make_config(table, precision, dt, skin, max_slots, max_particles)
+        self.pool = mdx.MdSystem(cfg, device=device)
+        self.chunk = int(chunk_steps)
+        self.max_slots = max_slots
+        self.make_system = make_system
+        self.free = list(range(max_slots))
+        self.running: Dict[int, dict] = {}
+
+    @staticmethod
+    def bytes_for_budget(table, precision, hbm_budget: float, max_slots: int,
+                         dt=0.001, skin=0.3) -> int:
+        """Largest arena (particles) whose workspace fits `hbm_budget` bytes."""
+        probe = mdx.make_config(table, precision, dt, skin, max_slots, 1 << 20)
+        per = mdx.md_workspace_bytes(probe) / (1 << 20)
+        return int(hbm_budget / per)
+
+    def _try_admit(self, job, system, now) -> bool:
+        if not self.free:
+            return False
+        slot = self.free[0]
+        try:
+            self.pool.attach(slot, system.n, system.box, system.species, system.pos, system.vel)
+        except mdx.MdError as e:
+            if e.status == -4:  # arena full: wait for a job to finish
+                return False
+            raise
+        self.free.pop(0)
+        self.pool.set_target(slot, job.steps)
+        self.running[slot] = {"job": job, "admitted": now}
+        return True
+
+    def run(self, jobs: List, time_scale: float = 1.0, log: Optional[Callable] = None) -> dict:
+        """Serve `jobs` (md_inputs.Job, sorted by arrival).  Arrival times are
+        in seconds of wall clock, multiplied by `time_scale`."""
+        pending = sorted(jobs, key=lambda j: j.arrival)
+        queue: List = []
+        results: List[JobResult] = []
+        t0 = time.perf_counter()
+        busy = 0.0
+        work = 0
+        pi = 0
+        while pi < len(pending) or queue or self.running:
+            now = time.perf_counter() - t0
+            while pi < len(pending) and pending[pi].arrival * time_scale <= now:
+                queue.append(pending[pi])
+                pi += 1
+            # admission in arrival order (head-of-line: a job that does not fit
+            # blocks later ones, so large jobs are not starved)
+            while queue:
+                job = queue[0]
+                sys_ = self.make_system(job)
+                if not self._try_admit(job, sys_, time.perf_counter() - t0):
+                    break
+                queue.pop(0)
+            if not self.running:
+                if pi < len(pending):  # idle until the next arrival
+                    time.sleep(max(0.0, pending[pi].arrival * time_scale - (time.perf_counter() - t0)))
+                continue
+            tb = time.perf_counter()
+            self.pool.advance(self.chunk)
+            steps, status = self.pool.poll()
+            busy += time.perf_counter() - tb
+            now = time.perf_counter() - t0
+            for slot in list(self.running):
+                r = self.running[slot]
+                job = r["job"]
+                if status[slot] & 0xFF:
+                    raise mdx.MdError(-4, f"job {job.job_id} failed with status {status[slot]}")
+                if steps[slot] >= job.steps and status[slot] & mdx.MD_ST_AT_FULL_STEP:
+                    pos, vel, img = self.pool.get_state(slot)
+                    results.append(JobResult(job.job_id, self.pool.sizes[slot], job.steps,
+                                             job.arrival * time_scale, r["admitted"], now,
+                                             pos, vel, img))
+                    work += self.pool.sizes[slot] * job.steps
+                    self.pool.detach(slot)
+                    self.free.append(slot)
+                    self.free.sort()
+                    del self.running[slot]
+                    if log:
+                        log(f"job {job.job_id} n={results[-1].n} steps={job.steps} "
+                            f"latency {results[-1].latency:.3f}s")
+        wall = time.perf_counter() - t0
+        lat = np.array([r.latency for r in results])
+        return {
+            "results": sorted(results, key=lambda r: r.job_id),
+            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "particle_steps": int(work),
+            "busy_s": busy,
+            "wall_s": wall,
+            "throughput_busy": work / busy if busy > 0 else None,
+            "throughput_wall": work / wall if wall > 0 else None,
+        }
+
+    def close(self):
+        self.pool.close()

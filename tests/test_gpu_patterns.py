@@ -1,0 +1,234 @@
+"""GPU tests of the systems patterns around the hot path, through the C ABI:
+bitwise independence of replicas in a batch, graph replay vs eager launches,
+launch shapes, split md_step calls, checkpoint/resume, the serving loop's
+alone-vs-mix results, the autotuner, double-single arithmetic against exact
+rational arithmetic, conservation laws, and error paths."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import md_inputs as I
+from gpu_helpers import pool_for, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(pool, slot=0):
+    p, v, i = pool.get_state(slot)
+    return p.copy(), v.copy(), i.copy()
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def _reps():
+    out = []
+    for k, (n, T) in enumerate([(600, 0.8), (1500, 0.5), (3001, 0.6), (5003, 0.45)]):
+        out.append(I.make_ka(n, T, jitter=0.05, seed=100 + k))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32", "fp64"])
+def test_batched_replicas_equal_alone(prec):
+    """Replicas of uneven N advanced together by one pool are bitwise equal to
+    the same replicas advanced alone (incl. one in single-cell mode)."""
+    reps = _reps()
+    say("batched vs alone", prec)
+    pool = pool_for(reps, prec)
+    pool.step(300)
+    batched = [_state(pool, k) for k in range(len(reps))]
+    obs = pool.observables()
+    assert all(o["n_rebuilds"] >= 2 for o in obs[:len(reps)])
+    pool.close()
+    for k, s in enumerate(reps):
+        alone = pool_for([s], prec)
+        alone.step(300)
+        assert _same(_state(alone), batched[k]), k
+        alone.close()
+
+
+def test_graph_eager_shapes_and_split_calls_are_bitwise_equal():
+    s = I.make_ka(4001, 0.7, jitter=0.05, seed=8)
+    say("graph/eager/shapes")
+    ref = None
+    for shape, calls in [(dict(graph_steps=32), [400]),
+                         (dict(graph_steps=0), [400]),
+                         (dict(graph_steps=8, step_block=64, build_width=2, build_block=128), [400]),
+                         (dict(graph_steps=32, step_block=1024, xcd_remap=1, build_width=16), [150, 1, 249]),
+                         (dict(graph_steps=2), [100, 100, 200])]:
+        pool = pool_for([s], "ds")
+        pool.set_launch(**shape)
+        for c in calls:
+            pool.step(c)
+        st = _state(pool)
+        if ref is None:
+            ref = st
+        assert _same(st, ref), shape
+        pool.close()
+
+
+@pytest.mark.parametrize("prec", ["ds", "mixed64", "fp64"])
+def test_checkpoint_resume_is_bitwise(prec):
+    s = I.make_ka(3001, 0.7, jitter=0.08, seed=9)
+    say("resume", prec)
+    pool = pool_for([s], prec)
+    pool.step(300)
+    ref = _state(pool)
+    pool.close()
+    a = pool_for([s], prec)
+    a.step(137)
+    blob = a.save(0)
+    a.close()
+    b = pool_for([I.make_ka(500, 0.5, seed=1)], prec, max_slots=2, extra_particles=s.n)
+    b.restore(1, blob, s.n, s.box)
+    b.step(163)
+    assert _same(_state(b, 1), ref)
+    b.close()
+
+
+def test_serving_results_equal_alone():
+    """Jobs served in a continuously batched pool (arrivals while others run,
+    slots and arena reused) end bitwise where they end alone."""
+    from paper_0912_3824_amd.serve import Server
+    jobs = I.serving_trace(7, rate_per_s=40.0, n_lo=500, n_hi=6000, steps_lo=150, steps_hi=700, seed=3)
+    say("serving", [(j.n, j.steps) for j in jobs])
+    srv = Server(I.ka_table(), "ds", max_slots=3, max_particles=12000, chunk_steps=64,
+                 make_system=lambda j: I.job_system(j))
+    out = srv.run(jobs)
+    srv.close()
+    assert len(out["results"]) == len(jobs)
+    assert out["p99_latency_s"] >= out["p50_latency_s"] > 0
+    for r, j in zip(out["results"], jobs):
+        alone = pool_for([I.job_system(j)], "ds")
+        alone.step(j.steps)
+        p, v, i = alone.get_state(0)
+        assert np.array_equal(p, r.pos) and np.array_equal(v, r.vel) and np.array_equal(i, r.image), j
+        alone.close()
+
+
+def test_autotuner_keeps_results():
+    from paper_0912_3824_amd import tune
+    s = I.make_ka(3001, 0.6, jitter=0.05, seed=12)
+    pool = pool_for([s], "ds")
+    ref_pool = pool_for([s], "ds")
+    res = tune.tune(pool, steps=20, space={"step_block": [128, 512], "build_width": [4, 8],
+                                          "build_block": [256], "graph_steps": [16], "xcd_remap": [0]},
+                    cache=None)
+    say("tuned", res["best"], res["us_per_step"])
+    assert len(res["all"]) == 4
+    pool.step(200)
+    ref_pool.step(200)
+    assert _same(_state(pool), _state(ref_pool))
+    pool.close()
+    ref_pool.close()
+
+
+def _exact(h, l):
+    return Fraction(float(h)) + Fraction(float(l))
+
+
+def test_double_single_arithmetic_against_exact_rationals():
+    """Device double-single add/sub/mul and the compensated sum against
+    Fraction arithmetic: relative error below 2^-44 (Sec. 2.4) apart from
+    cancellation, where the error is bounded by 2^-44 of the operands."""
+    import torch
+    from paper_0912_3824_amd import mdx
+    rng = np.random.default_rng(5)
+    n = 20000
+
+    def ds_of(x):
+        hi = x.astype(np.float32)
+        lo = (x - hi.astype(np.float64)).astype(np.float32)
+        return np.stack([hi, lo], 1)
+
+    x = rng.uniform(-1, 1, n) * 10.0 ** rng.integers(-6, 6, n)
+    y = rng.uniform(-1, 1, n) * 10.0 ** rng.integers(-6, 6, n)
+    y[: n // 10] = -x[: n // 10] * (1 + rng.uniform(-1e-6, 1e-6, n // 10))  # cancellation
+    a, b = ds_of(x), ds_of(y)
+    ta = torch.tensor(a, device="cuda")
+    tb = torch.tensor(b, device="cuda")
+    out = torch.empty_like(ta)
+    for op in (0, 1, 2):
+        mdx.md_ds_eval(op, ta, tb, out)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        worst = 0.0
+        for k in range(0, n, 7):
+            A, B = _exact(*a[k]), _exact(*b[k])
+            ex = A + B if op == 0 else (A - B if op == 1 else A * B)
+            got = _exact(*o[k])
+            scale = (abs(A) + abs(B)) if op < 2 else abs(ex)
+            if scale == 0:
+                continue
+            worst = max(worst, float(abs(got - ex) / scale))
+            assert abs(o[k, 1]) <= abs(float(np.spacing(o[k, 0]))) / 2 * (1 + 1e-6)  # normalised
+        say("op", op, "worst rel err", worst)
+        assert worst < 2.0 ** -44
+    # compensated sum of a force-like series (128 terms with cancellation):
+    # within the Sum2 bound (n u)^2 sum|x| of Ogita, Rump & Oishi, u = 2^-24
+    u = Fraction(1, 2 ** 24)
+    for trial in range(20):
+        vals = rng.normal(0, 10, 64).astype(np.float32)
+        vals = np.concatenate([vals, -vals[::-1] * np.float32(1 + 1e-5)]).astype(np.float32)
+        rng.shuffle(vals)
+        tv = torch.tensor(np.stack([vals, np.zeros_like(vals)], 1), device="cuda")
+        o2 = torch.empty(2, dtype=torch.float32, device="cuda")
+        mdx.md_ds_eval(3, tv, None, o2)
+        torch.cuda.synchronize()
+        got = _exact(*o2.cpu().numpy())
+        ex = sum(Fraction(float(v)) for v in vals)
+        assert abs(got - ex) <= (len(vals) * u) ** 2 * sum(abs(Fraction(float(v))) for v in vals)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "mixed64", "fp64"])
+def test_momentum_and_energy_conservation(prec):
+    s = I.make_ka(6000, 0.7, jitter=0.05, seed=21)
+    pool = pool_for([s], prec)
+    o0 = pool.observables()[0]
+    pool.step(2000)
+    o1 = pool.observables()[0]
+    dp = np.abs(o1["momentum"] - o0["momentum"]).max()
+    de = abs(o1["etot"] - o0["etot"]) / abs(o0["etot"])
+    say(prec, "dP", dp, "dE/E", de, "T", o1["temperature"])
+    # momentum: an FP32 force sum conserves it to ~1e-7 per particle-force,
+    # double-single / double sums far better
+    assert dp < (1e-2 if prec == "fp32" else 1e-6)
+    assert de < 1e-3
+    pool.close()
+
+
+def test_scale_velocities_sets_temperature():
+    s = I.make_ka(2000, 0.7, seed=3)
+    pool = pool_for([s], "ds")
+    pool.scale_velocities(0, math.sqrt(0.5 / 0.7))
+    assert pool.observables()[0]["temperature"] == pytest.approx(0.5, rel=1e-6)
+    pool.close()
+
+
+def test_error_paths():
+    from paper_0912_3824_amd import mdx
+    s = I.make_ka(2000, 0.7, seed=3)
+    # list capacity far too small: the first build overflows at attach
+    with pytest.raises(mdx.MdError) as ei:
+        pool_for([s], "ds", nbr_capacity=8)
+    assert ei.value.status == -4
+    # box too small for the list radius
+    small = I.make_ka(100, 0.7, seed=3)
+    with pytest.raises(mdx.MdError) as ei:
+        pool_for([small], "ds")
+    assert ei.value.status == -2
+    # arena too small for a second replica; slot reuse after detach
+    pool = pool_for([s], "ds", max_slots=2)
+    with pytest.raises(mdx.MdError) as ei:
+        pool.attach_system(1, s)
+    assert ei.value.status == -4
+    with pytest.raises(mdx.MdError):
+        pool.attach_system(0, s)   # slot busy
+    pool.detach(0)
+    pool.attach_system(1, s)
+    pool.step(10)
+    assert pool.observables()[1]["step"] == 10
+    pool.close()

@@ -97,7 +97,7 @@ struct md_system {
     int *count[2]{}, *cs = nullptr, *cs_new = nullptr;
     RepDev *rep = nullptr;
     Ctl *ctl[2]{};
-    int *target = nullptr, *need[2]{}, *status = nullptr, *nreb = nullptr;
+    int *target = nullptr, *need[2]{}, *rlist[2]{}, *status = nullptr, *nreb = nullptr;
     int *items3 = nullptr, *items4 = nullptr, *chunks = nullptr;
     double *partial = nullptr;
     // host state
@@ -234,6 +234,8 @@ static int64_t carve(md_system *s, const Layout &L, char *base)
     d->target = c.take<int>(L.slots);
     d->need[0] = c.take<int>(L.slots);
     d->need[1] = c.take<int>(L.slots);
+    d->rlist[0] = c.take<int>(L.slots + 1);
+    d->rlist[1] = c.take<int>(L.slots + 1);
     d->status = c.take<int>(L.slots);
     d->nreb = c.take<int>(L.slots);
     d->items3 = c.take<int>(L.slots + 1);
@@ -371,6 +373,8 @@ static StepArgs step_args(const md_system *s, int p)
     a.target = s->target;
     a.need_cur = s->need[p];
     a.need_other = s->need[p ^ 1];
+    a.rlist_cur = s->rlist[p];
+    a.rlist_other = s->rlist[p ^ 1];
     a.count_cur = s->count[p];
     a.count_other = s->count[p ^ 1];
     a.status = s->status;
@@ -390,6 +394,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     sa.force_slot = force_slot;
     sa.rep = s->rep;
     sa.need = s->need[p];
+    sa.rlist = s->rlist[p];
     sa.ctl = s->ctl[p ^ 1];
     sa.count = s->count[p];
     sa.cs_new = s->cs_new;
@@ -405,6 +410,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     pa.items_pref = s->items3;
     pa.rep = s->rep;
     pa.need = s->need[p];
+    pa.rlist = s->rlist[p];
     pa.ctl = s->ctl[p ^ 1];
     pa.cs = s->cs;
     pa.cs_new = s->cs_new;
@@ -427,6 +433,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     ba.items_pref = s->items4;
     ba.rep = s->rep;
     ba.need = s->need[p];
+    ba.rlist = s->rlist[p];
     ba.ctl = s->ctl[p ^ 1];
     ba.cs = s->cs;
     ba.cs_new = s->cs_new;
@@ -455,6 +462,7 @@ static md_status launch_build_main(md_system *s, int slot)
     ba.items_pref = s->items4;
     ba.rep = s->rep;
     ba.need = s->need[0];
+    ba.rlist = s->rlist[0];
     ba.ctl = s->ctl[0];
     ba.cs = s->cs;
     ba.cs_new = s->cs_new;
@@ -800,6 +808,7 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     for (int p = 0; p < 2; ++p) {
         if (!done(hipMemsetAsync(s->ctl[p], 0, sizeof(Ctl) * L.slots, st))) return MD_E_HIP;
         if (!done(hipMemsetAsync(s->need[p], 0, 4 * L.slots, st))) return MD_E_HIP;
+        if (!done(hipMemsetAsync(s->rlist[p], 0, 4 * (L.slots + 1), st))) return MD_E_HIP;
     }
     if (!done(hipMemsetAsync(s->target, 0, 4 * L.slots, st))) return MD_E_HIP;
     if (!done(hipMemsetAsync(s->status, 0, 4 * L.slots, st))) return MD_E_HIP;

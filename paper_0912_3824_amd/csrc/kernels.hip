@@ -55,11 +55,48 @@ __device__ __forceinline__ int find_item_slot(const int *pref, int nslots, int i
     return lo;
 }
 
+// Work-item walk of the rebuild kernels.  A step's rebuild (force_slot -1)
+// visits only the items of the slots on the rebuild list written by k_step;
+// a host-forced rebuild visits every item and filters by slot.  `unit` is
+// this worker's index among `nunits` workers; visit(slot, item) is called for
+// each item assigned to it.  Consecutive slots start on different workers so
+// that small replicas spread over the grid.
+template <class F>
+__device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
+                                          int max_slots, int force_slot, const Ctl *ctl, int which,
+                                          int unit, int nunits, F visit);
+
 __device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *need, const Ctl *ctl)
 {
-    if (force_slot == -1) return need[s] != 0;
+    if (force_slot == -1) return need && need[s] != 0;
     if (force_slot == -2) return ctl[s].z != 0;
     return s == force_slot;
+}
+
+template <class F>
+__device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
+                                          int max_slots, int force_slot, const Ctl *ctl, int which,
+                                          int unit, int nunits, F visit)
+{
+    if (force_slot == -1) {
+        const int cnt = rlist[0];
+        int cum = 0;
+        for (int li = 0; li < cnt; ++li) {
+            const int s = rlist[1 + li];
+            const int items = which == 3 ? rep[s].items3 : rep[s].items4;
+            int first = unit - cum % nunits;
+            first += first < 0 ? nunits : 0;
+            for (int it = first; it < items; it += nunits) visit(s, it);
+            cum += items;
+        }
+        return;
+    }
+    const int total = items_pref[max_slots];
+    for (int it = unit; it < total; it += nunits) {
+        const int s = find_item_slot(items_pref, max_slots, it);
+        if (!slot_selected(s, force_slot, nullptr, ctl)) continue;
+        visit(s, it - items_pref[s]);
+    }
 }
 
 __device__ __forceinline__ uint4 dbl2_to_u4(double a, double b)
@@ -408,9 +445,11 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     const int i = blk * blockDim.x + threadIdx.x;
     constexpr int NS = Traits<P>::NS;
 
-    if (!OBS) { // clear the other parity's cell counters (read by the last rebuild)
+    if (!OBS) { // clear the other parity's cell counters and rebuild list (read
+                // by the previous step's rebuild)
         const int gt = blockIdx.x * blockDim.x + threadIdx.x;
         for (int c = gt; c < a.cell_cap; c += nblk * blockDim.x) a.count_other[c] = 0;
+        if (gt == 0) a.rlist_other[0] = 0;
     }
     if (i >= A.P) return;
 
@@ -539,7 +578,10 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         cell = rp.nd == 1 ? 0 : fixed_cell(X.x, X.y, X.z, rp.nd);
     }
     atomicAdd(a.count_cur + rp.coff + cell, 1);
-    if (far) atomicOr(a.need_cur + r, 1);
+    if (far && atomicOr(a.need_cur + r, 1) == 0) { // first to flag: enlist the slot
+        const int k = atomicAdd(a.rlist_cur, 1);
+        a.rlist_cur[1 + k] = r;
+    }
     if (bad) atomicOr(a.status + r, 2);
 }
 
@@ -575,9 +617,14 @@ __global__ void k_count(const CountArgs a)
 // in tiles of 8 cells per thread, cell starts written as absolute slots.
 __global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
 {
-    const int s = blockIdx.x;
-    if (s >= a.max_slots) return;
-    if (!slot_selected(s, a.force_slot, a.need, a.ctl)) return;
+    int s = blockIdx.x;
+    if (a.force_slot == -1) {
+        if (s >= a.rlist[0]) return;
+        s = a.rlist[1 + s];
+    } else {
+        if (s >= a.max_slots) return;
+        if (!slot_selected(s, a.force_slot, a.need, a.ctl)) return;
+    }
     const RepDev rp = a.rep[s];
     const int ncell = rp.nd * rp.nd * rp.nd;
     const int B = blockDim.x, t = threadIdx.x;
@@ -710,12 +757,9 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
     const int wpb = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6;
     __shared__ int pref[4][28], pst[4][27];
-    const int total = a.items_pref[a.max_slots];
-    for (int item = blockIdx.x * wpb + wv; item < total; item += gridDim.x * wpb) {
-        const int s = find_item_slot(a.items_pref, a.max_slots, item);
-        if (!slot_selected(s, a.force_slot, a.need, a.ctl)) continue;
+    for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 3,
+              blockIdx.x * wpb + wv, gridDim.x * wpb, [&](int s, int c) {
         const RepDev rp = a.rep[s];
-        const int c = item - a.items_pref[s];
         const int nd = rp.nd;
         const int *cs = a.cs + rp.coff;
         const int dst0 = a.cs_new[rp.coff + c];
@@ -782,7 +826,7 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
         // neighbouring old cell; a shortfall means a particle jumped further
         if (lane == 0 && run != want) atomicOr(a.status + s, 4);
         __builtin_amdgcn_wave_barrier();
-    }
+    });
 }
 
 // ------------------------------------------------------------ k_build
@@ -826,85 +870,89 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         rl2s0 = (float)(rl2d0 / (u * u));
         rl2s1 = (float)(rl2d1 / (u * u));
     }
-    const int cap4 = A.cap >> 2;
-    int4 *rows = (int4 *)A.nbr_w + i;
-    int4 buf = make_int4(0, 0, 0, 0);
+    const int cap = A.cap;
+    // entry k of slot i: int4 row k/4, lane k%4 (see list_row)
+    int *col = A.nbr_w + 4 * (size_t)i;
+    const size_t row_stride = 4 * P_;
     int cnt = 0;
-    int pad = -1; // first candidate outside the list radius
-    auto scan_cell = [&](int k) {
+    int *wp = col; // where entry cnt goes
+    auto test = [&](int e, int st) -> bool {
+        if (NS == 2) {
+            double xj, yj, zj, wj;
+            if (FROM_LDS) {
+                u4_to_dbl2(cand[2 * (st + e)], xj, yj);
+                u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
+            } else {
+                u4_to_dbl2(a.src_x[st + e], xj, yj);
+                u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
+            }
+            double dx = xd - xj, dy = yd - yj, dz = zd - zj;
+            dx -= rp.L * rint(dx * rp.invL);
+            dy -= rp.L * rint(dy * rp.invL);
+            dz -= rp.L * rint(dz * rp.invL);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
+        }
+        const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+        const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
+                    dz = (float)(int)(xi.z - xj.z);
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
+    };
+    // Candidates of one cell in slot order; accepted ones are stored at once
+    // (a predicated 4-byte store).  `self` is the candidate index of i in
+    // this cell, or -1.
+    auto scan_cell = [&](int k, int self) {
         const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
         for (int e = 0; e < n; ++e) {
-            bool acc;
-            if (NS == 2) {
-                double xj, yj, zj, wj;
-                if (FROM_LDS) {
-                    u4_to_dbl2(cand[2 * (st + e)], xj, yj);
-                    u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
-                } else {
-                    u4_to_dbl2(a.src_x[st + e], xj, yj);
-                    u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
-                }
-                double dx = xd - xj, dy = yd - yj, dz = zd - zj;
-                dx -= rp.L * rint(dx * rp.invL);
-                dy -= rp.L * rint(dy * rp.invL);
-                dz -= rp.L * rint(dz * rp.invL);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                acc = r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
-            } else {
-                const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
-                const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
-                            dz = (float)(int)(xi.z - xj.z);
-                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                acc = r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
-            }
-            const int j = g0 + e;
-            pad = (!acc && pad < 0) ? j : pad;
-            if (acc && j != i) {
-                const int r = cnt & 3;
-                buf.x = r == 0 ? j : buf.x;
-                buf.y = r == 1 ? j : buf.y;
-                buf.z = r == 2 ? j : buf.z;
-                buf.w = r == 3 ? j : buf.w;
-                if (r == 3 && (cnt >> 2) < cap4) rows[(size_t)(cnt >> 2) * P_] = buf;
+            if (test(e, st) && e != self) {
+                if (cnt < cap) *wp = g0 + e;
                 ++cnt;
+                wp += (cnt & 3) ? 1 : (ptrdiff_t)row_stride - 3;
             }
         }
     };
+    int last_cell = 0;
     if (nd == 1) {
-        scan_cell(0);
+        scan_cell(0, i - T.glob[0]);
     } else {
-        // own cell, then each half-space offset o followed by -o
-        constexpr int H[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0}, {-1, -1, 1},
-                                  {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1}, {1, 0, 1},
-                                  {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
-        auto visit = [&](int dx, int dy, int dz) {
+        // own cell, then each half-space offset o followed by -o: in the
+        // (dz, dy, dx) enumeration of the 27 offsets the positive half space
+        // is indices 14..26
+        auto cell_k = [&](int dx, int dy, int dz) {
             int lx = lx_m + dx;
             if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
-            scan_cell(((dz + 1) * 3 + (dy + 1)) * NX + lx);
+            return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
         };
-        visit(0, 0, 0);
-#pragma unroll
-        for (int k = 0; k < 13; ++k) {
-            visit(H[k][0], H[k][1], H[k][2]);
-            visit(-H[k][0], -H[k][1], -H[k][2]);
+        const int own = cell_k(0, 0, 0);
+        scan_cell(own, i - T.glob[own]);
+        for (int q = 14; q < 27; ++q) {
+            const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
+            scan_cell(cell_k(dx, dy, dz), -1);
+            last_cell = cell_k(-dx, -dy, -dz);
+            scan_cell(last_cell, -1);
         }
     }
-    // Pad the last block of four with a particle that was outside the list
-    // radius at this build: it stays beyond the force cutoff until the next
-    // build (each particle moves at most skin/2), so the force loop needs no
-    // per-entry validity test.
-    // Lists are padded to a multiple of 8 entries (two blocks of four).
+    // Pad the list to a multiple of 8 with a particle that is outside the
+    // list radius at this build: it stays beyond the force cutoff until the
+    // next build (each particle moves at most skin/2), so the force loop
+    // needs no per-entry validity test.  The pad is the first rejected
+    // candidate of the last cell visited (a corner cell), else of any cell.
     if (cnt & 7) {
-        if (cnt & 3) {
-            const int r = cnt & 3;
-            buf.y = r <= 1 ? pad : buf.y;
-            buf.z = r <= 2 ? pad : buf.z;
-            buf.w = pad;
-            if ((cnt >> 2) < cap4) rows[(size_t)(cnt >> 2) * P_] = buf;
+        int pad = -1;
+        {
+            const int st = T.start[last_cell], n = T.cnt[last_cell], g0 = T.glob[last_cell];
+            for (int e = 0; e < n && pad < 0; ++e)
+                if (!test(e, st) && g0 + e != i) pad = g0 + e;
         }
-        const int q = (cnt + 3) >> 2; // first untouched block
-        if ((q & 1) && q < cap4) rows[(size_t)q * P_] = make_int4(pad, pad, pad, pad);
+        for (int k = 0; k < 9 * NX && pad < 0; ++k) {
+            const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+            for (int e = 0; e < n && pad < 0; ++e)
+                if (!test(e, st) && g0 + e != i) pad = g0 + e;
+        }
         if (pad < 0) atomicOr(a.status + s, 8);
+        for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
+            col[(size_t)(k >> 2) * row_stride + (k & 3)] = pad < 0 ? i : pad;
     }
     A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
     if (cnt > A.cap) atomicOr(a.status + s, 1);
@@ -935,14 +983,11 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
     constexpr int NS = Traits<P>::NS;
     __shared__ BuildTabs T;
     extern __shared__ uint4 cand[];
-    const int total_items = a.items_pref[a.max_slots];
     const int B = blockDim.x, t = threadIdx.x;
-    for (int it = remap_block(blockIdx.x, gridDim.x, a.xcd); it < total_items; it += gridDim.x) {
-        const int s = find_item_slot(a.items_pref, a.max_slots, it);
-        if (!slot_selected(s, a.force_slot, a.need, a.ctl)) continue;
+    for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 4,
+              remap_block(blockIdx.x, gridDim.x, a.xcd), gridDim.x, [&](int s, int item) {
         const RepDev rp = a.rep[s];
         const int nd = rp.nd;
-        const int item = it - a.items_pref[s];
         const int *cs = a.cs_new + rp.coff;
         int m0, m1, NX = 1, x0 = 0, x1 = 1, rowbase = 0;
         bool full = true;
@@ -1052,7 +1097,7 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             copy_back<P>(a, i);
         }
         __syncthreads();
-    }
+    });
 }
 
 // ------------------------------------------------------------ k_obs_reduce

@@ -27,6 +27,7 @@ struct StepArgs {
     Ctl *ctl_next;
     const int *target;
     int *need_cur, *need_other;
+    int *rlist_cur, *rlist_other; // [0] = count, [1..] = slots that must rebuild
     int *count_cur, *count_other;
     int *status;
     double *obs;
@@ -46,6 +47,7 @@ struct ScanArgs {
     int max_slots, force_slot;
     const RepDev *rep;
     const int *need;
+    const int *rlist;
     const Ctl *ctl;
     const int *count;
     int *cs_new;
@@ -59,6 +61,7 @@ struct PermArgs {
     const int *items_pref;
     const RepDev *rep;
     const int *need;
+    const int *rlist;
     const Ctl *ctl;
     const int *cs, *cs_new;
     const uint4 *snap;
@@ -74,6 +77,7 @@ struct BuildArgs {
     const int *items_pref;
     const RepDev *rep;
     const int *need;
+    const int *rlist;
     const Ctl *ctl;
     int *cs;
     const int *cs_new;

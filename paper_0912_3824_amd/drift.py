@@ -78,7 +78,7 @@ def run(n: int = 64000, temperature: float = 0.7, steps: int = 100000, every: in
     the same state for `steps` NVE steps in every precision."""
     sys.path.insert(0, __file__.rsplit("/", 2)[0])
     import md_inputs as I
-    from . import mdx
+    from paper_0912_3824_amd import mdx
     s = I.make_ka(n, temperature, seed=seed)
     pool = mdx.md_init([s], "fp64")
     done = 0

@@ -1,0 +1,134 @@
+"""Measurements of the batching and serving patterns against plain
+single-system runs of the same replicas (equal arithmetic, bitwise-equal
+results).
+
+  python -m paper_0912_3824_amd.patterns_bench batch [--replicas 256 --steps 2000]
+  python -m paper_0912_3824_amd.patterns_bench serve [--jobs 40 --load 0.8]
+
+batch: 256 Kob-Andersen replicas, N log-uniform in [500, 8000], rho = 1.2,
+       T from {0.45, 0.5, 0.6, 0.8}, advanced together in one pool (one
+       fused launch per step for all replicas, graph-captured); compared with
+       a sample of the same replicas advanced one at a time.
+serve: Poisson arrivals of KA jobs, N log-uniform in [1000, 256000], steps
+       uniform in [steps_lo, steps_hi], T uniform in [0.45, 1.0]; admission
+       by arena footprint; p50/p99 latency and throughput over the busy
+       period, against the same jobs run one after another alone.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print("[patterns]", *a, file=sys.stderr, flush=True)
+
+
+def _timed_step(pool, steps):
+    import torch
+    pool.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pool.step(steps)
+    pool.sync()
+    return time.perf_counter() - t0
+
+
+def batch(n_rep=256, steps=2000, warmup=200, alone_sample=16, precision="ds", seed=20240101):
+    import md_inputs as I
+    from paper_0912_3824_amd import mdx, tune
+    reps = I.make_ka_ensemble(n_rep, seed=seed)
+    total = sum(r.n for r in reps)
+    pool = mdx.md_init(reps, precision)
+    tune.apply_cached(pool)
+    pool.step(warmup)
+    t = _timed_step(pool, steps)
+    obs = pool.observables()
+    assert not any(o["status"] for o in obs if o["n"])
+    prof = pool.profile_steps(100)
+    pool.close()
+    batched = total * steps / t
+    log(f"batch: {n_rep} replicas, {total} particles, {t / steps * 1e6:.1f} us/step, {batched:.4g} p-s/s")
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(n_rep, size=min(alone_sample, n_rep), replace=False))
+    work, wall = 0, 0.0
+    for k in idx:
+        p = mdx.md_init([reps[k]], precision)
+        p.step(warmup)
+        dt = _timed_step(p, steps)
+        work += reps[k].n * steps
+        wall += dt
+        p.close()
+    alone = work / wall
+    log(f"alone (sample of {len(idx)}): {alone:.4g} p-s/s")
+    return {"replicas": n_rep, "particles": total, "steps": steps, "precision": precision,
+            "batched_particle_steps_per_s": batched, "batched_us_per_step": t / steps * 1e6,
+            "alone_particle_steps_per_s": alone, "alone_sample": int(len(idx)),
+            "speedup_vs_alone": batched / alone, "step_kernel_ms": prof["step_kernel_ms"],
+            "rebuild_group_ms_mean": prof["rebuild_ms_mean"]}
+
+
+def serve(n_jobs=40, load=0.8, steps_lo=1000, steps_hi=10000, n_lo=1000, n_hi=256000,
+          max_slots=32, hbm_budget_gb=4.0, chunk=256, precision="ds", seed=20240101):
+    import md_inputs as I
+    from paper_0912_3824_amd import mdx
+    from paper_0912_3824_amd.serve import Server
+    # capacity estimate: the throughput of a mid-size replica alone
+    probe = I.make_ka(64000, 0.7, seed=seed)
+    p = mdx.md_init([probe], precision)
+    p.step(100)
+    cap = probe.n * 1000 / _timed_step(p, 1000)
+    p.close()
+    mean_job = math.exp((math.log(n_hi) + math.log(n_lo)) / 2) * 1.15 * (steps_lo + steps_hi) / 2
+    rate = load * cap / mean_job
+    jobs = I.serving_trace(n_jobs, rate, n_lo=n_lo, n_hi=n_hi, steps_lo=steps_lo,
+                           steps_hi=steps_hi, seed=seed)
+    max_particles = Server.bytes_for_budget(I.ka_table(), precision, hbm_budget_gb * 1e9, max_slots)
+    log(f"serve: {n_jobs} jobs at {rate:.2f}/s (offered load {load}), arena {max_particles} particles")
+    srv = Server(I.ka_table(), precision, max_slots=max_slots, max_particles=max_particles,
+                 chunk_steps=chunk, make_system=lambda j: I.job_system(j))
+    out = srv.run(jobs)
+    srv.close()
+    # the same jobs, one after another, each alone
+    work, wall = 0, 0.0
+    for j in jobs:
+        s = I.job_system(j)
+        q = mdx.md_init([s], precision)
+        wall += _timed_step(q, j.steps)
+        work += s.n * j.steps
+        q.close()
+    res = {k: v for k, v in out.items() if k != "results"}
+    res.update({"jobs": n_jobs, "rate_per_s": rate, "offered_load": load, "max_slots": max_slots,
+                "arena_particles": max_particles, "chunk_steps": chunk, "precision": precision,
+                "alone_sequential_particle_steps_per_s": work / wall,
+                "served_vs_alone": res["throughput_busy"] / (work / wall),
+                "latencies_s": [round(r.latency, 4) for r in out["results"]]})
+    log(json.dumps({k: v for k, v in res.items() if k != "latencies_s"}))
+    return res
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["batch", "serve"])
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--jobs", type=int, default=40)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--steps-lo", type=int, default=1000)
+    ap.add_argument("--steps-hi", type=int, default=10000)
+    ap.add_argument("--precision", default="ds")
+    a = ap.parse_args()
+    if a.mode == "batch":
+        r = batch(a.replicas, a.steps, precision=a.precision)
+    else:
+        r = serve(a.jobs, a.load, a.steps_lo, a.steps_hi, precision=a.precision)
+    print(json.dumps(r))

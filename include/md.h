@@ -104,6 +104,12 @@ typedef struct {
     int64_t max_particles; /* particle arena capacity; >= 1 */
     int64_t max_cells;     /* cell arena capacity; 0 = derive from max_particles */
     double max_density;    /* density used to derive capacities; 0 = 1.2 */
+    int32_t lanes_per_particle; /* lanes summing one particle's list: 1, 2 or 4
+                                   (0 = 2).  Part of the arithmetic: the force
+                                   sum is split into this many partial sums,
+                                   combined in a fixed order, so results are
+                                   bitwise reproducible for a given value. */
+    int32_t reserved;
 } md_config;
 
 /* One replica: N particles in a cubic box of edge `box`. */

@@ -25,7 +25,8 @@ constexpr int64_t ALIGN = 256;
 constexpr int GRID_PERM = 2048;   // persistent grids of the rebuild kernels
 constexpr int GRID_BUILD = 1024;
 constexpr uint32_t CKPT_MAGIC = 0x4d445843; // "MDXC"
-constexpr int CKPT_VERSION = 1;
+constexpr int CKPT_VERSION = 2;
+constexpr int MD_DEFAULT_LPP = 2;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -108,6 +109,7 @@ struct md_system {
     std::vector<SlotHost> slots;
     RangeAlloc parena, carena;
     int parity = 0; // parity of the snapshot the next step reads
+    int lpp = 1;    // lanes per particle of the force sum
     std::map<int, hipGraphExec_t> graphs;
     std::string err;
 };
@@ -174,6 +176,9 @@ static md_status validate_cfg(const md_config *c, std::string *why)
     if (c->nbr_capacity < 0 || c->nbr_capacity > 4096) return bad("nbr_capacity must be in [0, 4096]");
     if (c->max_cells < 0) return bad("max_cells must be >= 0");
     if (c->max_density < 0) return bad("max_density must be >= 0");
+    if (c->lanes_per_particle != 0 && c->lanes_per_particle != 1 && c->lanes_per_particle != 2 &&
+        c->lanes_per_particle != 4)
+        return bad("lanes_per_particle must be 0, 1, 2 or 4");
     return MD_OK;
 }
 
@@ -365,6 +370,7 @@ static StepArgs step_args(const md_system *s, int p)
     a.cell_cap = (int)s->lay.cells;
     a.max_slots = (int)s->lay.slots;
     a.xcd = s->launch.xcd_remap;
+    a.lpp = s->lpp;
     a.snap_cur = s->snap[p];
     a.snap_next = s->snap[p ^ 1];
     a.rep = s->rep;
@@ -779,6 +785,7 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     md_system *s = new md_system();
     s->cfg = *cfg;
     s->prec = cfg->precision;
+    s->lpp = cfg->lanes_per_particle > 0 ? cfg->lanes_per_particle : MD_DEFAULT_LPP;
     s->lay = L;
     s->stream = (hipStream_t)hip_stream;
     s->ws = (char *)workspace;
@@ -1232,7 +1239,7 @@ md_status md_get_state(md_system *s, int32_t slot, double *pos, double *vel, int
 
 struct CkptHeader {
     uint32_t magic;
-    int32_t version, precision, n_species, n, NW, NS, nd;
+    int32_t version, precision, n_species, n, NW, NS, nd, lpp;
     double L, dt, skin, mass, eps[4], sigma[4], rcut[4];
     int64_t step, fresh, nreb, status;
 };
@@ -1269,6 +1276,7 @@ md_status md_save(md_system *s, int32_t slot, void *blob, int64_t bytes)
     H.NW = s->lay.NW;
     H.NS = s->lay.NS;
     H.nd = h.nd;
+    H.lpp = s->lpp;
     H.L = h.L;
     H.dt = s->cfg.dt;
     H.skin = s->cfg.skin;
@@ -1299,7 +1307,7 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
     CkptHeader H;
     memcpy(&H, blob, sizeof H);
     if (H.magic != CKPT_MAGIC || H.version != CKPT_VERSION) return fail(s, MD_E_ARG, "not a checkpoint");
-    if (H.precision != s->prec || H.n_species != s->cfg.n_species || H.dt != s->cfg.dt || H.skin != s->cfg.skin ||
+    if (H.precision != s->prec || H.lpp != s->lpp || H.n_species != s->cfg.n_species || H.dt != s->cfg.dt || H.skin != s->cfg.skin ||
         H.mass != s->cfg.mass || memcmp(H.eps, s->cfg.eps, sizeof H.eps) || memcmp(H.sigma, s->cfg.sigma, sizeof H.sigma) ||
         memcmp(H.rcut, s->cfg.rcut, sizeof H.rcut))
         return fail(s, MD_E_ARG, "checkpoint from an incompatible pool");

@@ -207,6 +207,17 @@ template <> struct FAcc<PREC_MIX> {
     __device__ void get(double &fx, double &fy, double &fz) const { fx = x; fy = y; fz = z; }
 };
 
+// Butterfly sum of the partial sums of the LPP lanes that share a particle
+// (lanes 2^k apart exchange; every step is a commutative add, so all lanes
+// of the group end with the same bits).
+__device__ __forceinline__ void lane_sum(float &x, int m) { x += __shfl_xor(x, m, 64); }
+__device__ __forceinline__ void lane_sum(double &x, int m) { x += __shfl_xor(x, m, 64); }
+__device__ __forceinline__ void lane_sum(dsf &x, int m)
+{
+    dsf o = {__shfl_xor(x.hi, m, 64), __shfl_xor(x.lo, m, 64)};
+    x = ds_add(x, o);
+}
+
 // ------------------------------------------------------------ integration
 // Velocity-Verlet pieces: kick v += (dt/2m) F, drift r += dt v.
 __device__ __forceinline__ void kick(State<PREC_FP32> &s, const FAcc<PREC_FP32> &f, const IntegDev &g)
@@ -347,24 +358,26 @@ __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int j)
 template <int P, bool EN, bool UNI>
 __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
                                             uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
-                                            FAcc<P> &acc, double &e_sum, double &w_sum)
+                                            FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp)
 {
     const int cnt = A.nbr_cnt[i];
     const int nq = ((cnt + 7) >> 3) << 1; // blocks of four, padded to an even count
     acc.init();
-    if (nq == 0) return;
+    const int npair = nq >> 1;            // this lane takes pairs sub, sub + lpp, ...
+    if (sub >= npair) return;
     const int last = nq - 1;
+    int p = sub;
     // indices two blocks ahead, snapshots one block ahead
-    int4 ja = list_row(A, i, 0), jb = list_row(A, i, 1);
+    int4 ja = list_row(A, i, 2 * p), jb = list_row(A, i, 2 * p + 1);
     uint4 a0 = ld_snap(snap, ja.x), a1 = ld_snap(snap, ja.y), a2 = ld_snap(snap, ja.z),
           a3 = ld_snap(snap, ja.w);
-    ja = list_row(A, i, min(2, last));
-    for (int q = 0; q < nq; q += 2) {
+    ja = list_row(A, i, min(2 * (p + lpp), last));
+    for (; p < npair; p += lpp) {
         // (the scheduling barriers keep each batch of loads ahead of the
         // block computed while it is in flight)
         const uint4 b0 = ld_snap(snap, jb.x), b1 = ld_snap(snap, jb.y), b2 = ld_snap(snap, jb.z),
                     b3 = ld_snap(snap, jb.w);
-        jb = list_row(A, i, min(q + 3, last));
+        jb = list_row(A, i, min(2 * (p + lpp) + 1, last));
         __builtin_amdgcn_sched_barrier(0);
         entry_fixed<P, EN, UNI>(xi, a0, c, pp, si, acc, e_sum, w_sum);
         entry_fixed<P, EN, UNI>(xi, a1, c, pp, si, acc, e_sum, w_sum);
@@ -375,7 +388,7 @@ __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__rest
         a1 = ld_snap(snap, ja.y);
         a2 = ld_snap(snap, ja.z);
         a3 = ld_snap(snap, ja.w);
-        ja = list_row(A, i, min(q + 4, last));
+        ja = list_row(A, i, min(2 * (p + 2 * lpp), last));
         __builtin_amdgcn_sched_barrier(0);
         entry_fixed<P, EN, UNI>(xi, b0, c, pp, si, acc, e_sum, w_sum);
         entry_fixed<P, EN, UNI>(xi, b1, c, pp, si, acc, e_sum, w_sum);
@@ -389,7 +402,7 @@ __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__rest
 __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restrict__ snap, int i,
                                           double xi, double yi, double zi, int si, const RepDev &r,
                                           const PairDev &pp, double &fx, double &fy, double &fz,
-                                          bool en, double &e_sum, double &w_sum)
+                                          bool en, double &e_sum, double &w_sum, int sub, int lpp)
 {
     const int cnt = A.nbr_cnt[i];
     const size_t P_ = (size_t)A.P;
@@ -400,7 +413,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
     sig2[0] = pp.sig2d[si * 2]; sig2[1] = pp.sig2d[si * 2 + 1];
     e24[0] = pp.eps24d[si * 2]; e24[1] = pp.eps24d[si * 2 + 1];
     const int nq = ((cnt + 7) >> 3) << 1;
-    for (int q = 0; q < nq; ++q) {
+    for (int q = sub; q < nq; q += lpp) {
         const int4 jj = list_row(A, i, q);
         const int js[4] = {jj.x, jj.y, jj.z, jj.w};
 #pragma unroll
@@ -436,13 +449,15 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
 // ------------------------------------------------------------ k_step
 enum { M_ADV = 0, M_FIN = 1, M_IDLE = 2 };
 
-template <int P, bool OBS, bool UNI>
+template <int P, bool OBS, bool UNI, int LPP>
 __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
 {
     const KArena &A = a.A;
     const int nblk = gridDim.x;
     const int blk = remap_block(blockIdx.x, nblk, a.xcd);
-    const int i = blk * blockDim.x + threadIdx.x;
+    const int gid = blk * blockDim.x + threadIdx.x;
+    const int i = gid / LPP;   // LPP adjacent lanes share particle i
+    const int sub = gid % LPP;
     constexpr int NS = Traits<P>::NS;
 
     if (!OBS) { // clear the other parity's cell counters and rebuild list (read
@@ -476,7 +491,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     } else {
         const int tgt = a.target[r];
         mode = ctl.x < tgt ? M_ADV : (ctl.y ? M_IDLE : M_FIN);
-        if (i == rp.off) { // the replica's first particle owns its control words
+        if (i == rp.off && sub == 0) { // the replica's first particle owns its control words
             Ctl nx = ctl;
             if (mode == M_ADV) { nx.x = ctl.x + 1; nx.y = 0; }
             else nx.y = 1;
@@ -484,8 +499,10 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
             a.need_other[r] = 0;
         }
         if (mode == M_IDLE) {
-            a.snap_next[i] = s0;
-            if (NS == 2) a.snap_next[(size_t)A.P + i] = s1;
+            if (sub == 0) {
+                a.snap_next[i] = s0;
+                if (NS == 2) a.snap_next[(size_t)A.P + i] = s1;
+            }
             return;
         }
     }
@@ -500,7 +517,13 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         double xi, yi, zi, wi;
         u4_to_dbl2(s0, xi, yi);
         u4_to_dbl2(s1, zi, wi);
-        force_dbl(A, a.snap_cur, i, xi, yi, zi, si, rp, a.pp, fxd, fyd, fzd, OBS, e_sum, w_sum);
+        force_dbl(A, a.snap_cur, i, xi, yi, zi, si, rp, a.pp, fxd, fyd, fzd, OBS, e_sum, w_sum, sub, LPP);
+#pragma unroll
+        for (int m = 1; m < LPP; m <<= 1) {
+            lane_sum(fxd, m); lane_sum(fyd, m); lane_sum(fzd, m);
+            if (OBS) { lane_sum(e_sum, m); lane_sum(w_sum, m); }
+        }
+        if (sub != 0) return;
         if (OBS) {
             double *o = a.obs + (size_t)i * 8;
             o[0] = fxd; o[1] = fyd; o[2] = fzd; o[3] = e_sum; o[4] = w_sum;
@@ -515,9 +538,20 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     } else {
         const LaneConsts c = lane_consts(a.pp, si, rp);
         FAcc<P> acc;
-        force_fixed<P, OBS, UNI>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum);
+        force_fixed<P, OBS, UNI>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum, sub, LPP);
+        // combine the lanes' partial sums (a no-op for one lane per particle)
+        DsForce F;
+        if constexpr (P == PREC_DS) F = {acc.x.result(), acc.y.result(), acc.z.result()};
+#pragma unroll
+        for (int m = 1; m < LPP; m <<= 1) {
+            if constexpr (P == PREC_DS) { lane_sum(F.x, m); lane_sum(F.y, m); lane_sum(F.z, m); }
+            else { lane_sum(acc.x, m); lane_sum(acc.y, m); lane_sum(acc.z, m); }
+            if (OBS) { lane_sum(e_sum, m); lane_sum(w_sum, m); }
+        }
+        if (sub != 0) return;
         if (OBS) {
-            acc.get(fxd, fyd, fzd);
+            if constexpr (P == PREC_DS) { fxd = ds_to_double(F.x); fyd = ds_to_double(F.y); fzd = ds_to_double(F.z); }
+            else acc.get(fxd, fyd, fzd);
             double *o = a.obs + (size_t)i * 8;
             o[0] = fxd; o[1] = fyd; o[2] = fzd; o[3] = e_sum; o[4] = w_sum;
             double vx, vy, vz;
@@ -531,7 +565,6 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
             if (!ctl.y) kick(st, acc, a.ig);
             if (mode == M_ADV) { kick(st, acc, a.ig); drift(st, a.ig); }
         } else if constexpr (P == PREC_DS) {
-            DsForce F = {acc.x.result(), acc.y.result(), acc.z.result()};
             if (!ctl.y) kick(st, F, a.ig);
             if (mode == M_ADV) { kick(st, F, a.ig); drift(st, a.ig); }
         } else { // MIXED64: FP64 sum of FP32 pair terms
@@ -902,15 +935,26 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
     // Candidates of one cell in slot order; accepted ones are stored at once
     // (a predicated 4-byte store).  `self` is the candidate index of i in
     // this cell, or -1.
+    auto put = [&](bool acc, int j) {
+        if (acc) {
+            if (cnt < cap) *wp = j;
+            ++cnt;
+            wp += (cnt & 3) ? 1 : (ptrdiff_t)row_stride - 3;
+        }
+    };
+    // four candidates per iteration: independent reads and tests in flight
+    // (the scan is a dependent chain per member), stores in slot order
     auto scan_cell = [&](int k, int self) {
         const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
-        for (int e = 0; e < n; ++e) {
-            if (test(e, st) && e != self) {
-                if (cnt < cap) *wp = g0 + e;
-                ++cnt;
-                wp += (cnt & 3) ? 1 : (ptrdiff_t)row_stride - 3;
-            }
+        int e = 0;
+        for (; e + 4 <= n; e += 4) {
+            const bool c0 = test(e, st), c1 = test(e + 1, st), c2 = test(e + 2, st), c3 = test(e + 3, st);
+            put(c0 && e != self, g0 + e);
+            put(c1 && e + 1 != self, g0 + e + 1);
+            put(c2 && e + 2 != self, g0 + e + 2);
+            put(c3 && e + 3 != self, g0 + e + 3);
         }
+        for (; e < n; ++e) put(test(e, st) && e != self, g0 + e);
     };
     int last_cell = 0;
     if (nd == 1) {
@@ -1204,16 +1248,25 @@ __global__ void k_ds_eval(int op, long long n, const float *a, const float *b, f
 // ------------------------------------------------------------ launchers
 #define LAUNCH_CHECK() return hipGetLastError()
 
+template <int P, int LPP>
+static hipError_t launch_step_l(const StepArgs &a, int block, bool obs, hipStream_t s)
+{
+    const long long threads = (long long)a.A.P * LPP;
+    const int grid = (int)((threads + block - 1) / block);
+    const bool uni = a.pp.uniform != 0 && P != PREC_FP64;
+    if (obs && uni) hipLaunchKernelGGL((k_step<P, true, true, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else if (obs) hipLaunchKernelGGL((k_step<P, true, false, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else if (uni) hipLaunchKernelGGL((k_step<P, false, true, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, false, false, LPP>), dim3(grid), dim3(block), 0, s, a);
+    LAUNCH_CHECK();
+}
+
 template <int P>
 static hipError_t launch_step_t(const StepArgs &a, int block, bool obs, hipStream_t s)
 {
-    int grid = (a.A.P + block - 1) / block;
-    const bool uni = a.pp.uniform != 0 && P != PREC_FP64;
-    if (obs && uni) hipLaunchKernelGGL((k_step<P, true, true>), dim3(grid), dim3(block), 0, s, a);
-    else if (obs) hipLaunchKernelGGL((k_step<P, true, false>), dim3(grid), dim3(block), 0, s, a);
-    else if (uni) hipLaunchKernelGGL((k_step<P, false, true>), dim3(grid), dim3(block), 0, s, a);
-    else hipLaunchKernelGGL((k_step<P, false, false>), dim3(grid), dim3(block), 0, s, a);
-    LAUNCH_CHECK();
+    if (a.lpp == 4) return launch_step_l<P, 4>(a, block, obs, s);
+    if (a.lpp == 2) return launch_step_l<P, 2>(a, block, obs, s);
+    return launch_step_l<P, 1>(a, block, obs, s);
 }
 
 hipError_t launch_step(int prec, const StepArgs &a, int block, bool obs, hipStream_t s)

@@ -19,7 +19,7 @@ struct KArena {
 
 struct StepArgs {
     KArena A;
-    int cell_cap, max_slots, xcd, pad0;
+    int cell_cap, max_slots, xcd, lpp; // lpp: lanes per particle (1, 2, 4)
     const uint4 *snap_cur;
     uint4 *snap_next;
     const RepDev *rep;

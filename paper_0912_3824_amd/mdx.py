@@ -44,7 +44,8 @@ class MdConfig(ctypes.Structure):
                 ("dt", ctypes.c_double), ("skin", ctypes.c_double),
                 ("nbr_capacity", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("max_particles", ctypes.c_int64), ("max_cells", ctypes.c_int64),
-                ("max_density", ctypes.c_double)]
+                ("max_density", ctypes.c_double), ("lanes_per_particle", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class MdReplica(ctypes.Structure):
@@ -150,7 +151,8 @@ def _ip(a: np.ndarray):
 
 def make_config(table, precision, dt: float, skin: float, max_slots: int,
                 max_particles: int, mass: float = 1.0, nbr_capacity: int = 0,
-                max_cells: int = 0, max_density: float = 0.0) -> MdConfig:
+                max_cells: int = 0, max_density: float = 0.0,
+                lanes_per_particle: int = 0) -> MdConfig:
     """md_config from a pair table (md_inputs.PairTable) and run parameters."""
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
@@ -168,6 +170,7 @@ def make_config(table, precision, dt: float, skin: float, max_slots: int,
     c.max_particles = int(max_particles)
     c.max_cells = int(max_cells)
     c.max_density = float(max_density)
+    c.lanes_per_particle = int(lanes_per_particle)
     return c
 
 

@@ -24,11 +24,11 @@ def _ka(n, T=0.7, seed=11, jitter=0.06):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n", [500, 3001, 12007])
-def test_forces_match_oracle(prec, n):
+@pytest.mark.parametrize("n,lpp", [(500, 0), (3001, 1), (3001, 4), (12007, 0)])
+def test_forces_match_oracle(prec, n, lpp):
     s = _ka(n)
-    say("forces", prec, n)
-    pool = pool_for([s], prec)
+    say("forces", prec, n, "lanes", lpp)
+    pool = pool_for([s], prec, lanes_per_particle=lpp)
     pos, vel, img = pool.get_state(0)
     f, e = pool.forces(0)
     fr, er, wr = O.forces(pos, s.box, s.species, s.table)
@@ -72,10 +72,11 @@ def test_neighbour_lists_match_oracle(prec, n, width):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_ten_step_trajectory(prec):
+@pytest.mark.parametrize("lpp", [1, 2, 4])
+def test_ten_step_trajectory(prec, lpp):
     s = _ka(3001, T=0.7)
-    say("10-step", prec)
-    pool = pool_for([s], prec)
+    say("10-step", prec, "lanes", lpp)
+    pool = pool_for([s], prec, lanes_per_particle=lpp)
     p0, v0, i0 = pool.get_state(0)
     pool.step(10)
     p1, v1, i1 = pool.get_state(0)

@@ -12,7 +12,6 @@ Prints ONE JSON line on stdout; diagnostics go to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ka1m]
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -54,14 +53,6 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "md_dev.hpp", "ds.hpp", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_0912_3824_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(workload: str, prec: str, n_particles: int):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -70,7 +61,8 @@ def read_traffic(workload: str, prec: str, n_particles: int):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_hash") != kernel_hash():
+    from paper_0912_3824_amd.profiling import kernel_source_hash
+    if d.get("kernel_hash") != kernel_source_hash():
         return None
     return d.get("hbm_bytes_per_launch")
 

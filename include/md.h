@@ -143,7 +143,12 @@ typedef struct {
     int32_t build_block;   /* threads per block of the list build: 64..1024, multiple of 64 */
     int32_t graph_steps;   /* steps per captured hipGraph (even, 2..256); 0 = no graphs */
     int32_t xcd_remap;     /* 1 = map consecutive particle tiles to one XCD (8 XCDs) */
-    int32_t reserved[3];
+    int32_t build_lanes;   /* lanes that build one particle's list together: 1, 2, 4, .., 64;
+                            * 0 = automatic: one lane for replicas with >= 256 row segments;
+                            * smaller replicas split each segment's members over several
+                            * work items, each using the most lanes that keep one group per
+                            * member (16 for single-cell replicas) */
+    int32_t reserved[2];
 } md_launch;
 
 /* ---- sizing and lifetime ------------------------------------------------ */
@@ -238,10 +243,14 @@ md_status md_scale_velocities(md_system *sys, int32_t slot, double factor);
 
 /* Benchmark helper: advance every attached replica by n_steps like md_step
  * but with eager launches, timing each step's fused kernel and its group of
- * rebuild kernels with hipEvents recorded on the pool's stream.  out[5]:
+ * rebuild kernels with hipEvents recorded on the pool's stream.  The launches
+ * are issued back to back (no host synchronisation between steps; per-step
+ * rebuild counters are copied to pinned host memory on the stream), so the
+ * kernels run as they do in md_step.  n_steps in [1, 65536].  out[5]:
  * [0] mean fused-kernel ms, [1] mean rebuild-group ms over all steps,
  * [2] mean rebuild-group ms over steps in which a replica rebuilt,
- * [3] number of such steps, [4] total GPU ms of the n_steps.  Synchronises. */
+ * [3] number of such steps, [4] total GPU ms of the n_steps.  Synchronises.
+ * Allocates pinned host memory for the duration of the call. */
 md_status md_profile_steps(md_system *sys, int64_t n_steps, double *out);
 
 /* Block until all work on the pool's stream has finished. */

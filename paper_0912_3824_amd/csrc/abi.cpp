@@ -308,12 +308,47 @@ static int cells_per_edge(double L, double rl)
     return nd;
 }
 
+// members per list-build work item of a single-cell replica: one group of
+// build_lanes lanes (16 when automatic) per member
+static int single_members(const md_system *s)
+{
+    const int G = s->launch.build_lanes ? s->launch.build_lanes : 16;
+    return std::max(1, s->launch.build_block / G);
+}
+
+// Work decomposition of the list build of one replica.  A replica with at
+// least one row segment per compute unit builds one segment per work item,
+// one lane per member.  A smaller one (whose build would otherwise run on a
+// few CUs, each testing every member against hundreds of candidates) splits
+// each segment's members over up to 256 / segments work items (at least 16
+// members each) and lets a group of lanes share each member's candidates.
+// None of this changes a list entry.
+static void build_shape(const md_system *s, int n, int nd, int &parts, int &lanes)
+{
+    parts = 1;
+    lanes = s->launch.build_lanes;
+    if (nd == 1) return;
+    const int W = s->launch.build_width;
+    const int nseg = nd <= W + 2 ? 1 : (nd + W - 1) / W;
+    const int base = nd * nd * nseg;
+    if (base >= 256) {
+        if (!lanes) lanes = 1;
+        return;
+    }
+    parts = std::max(1, std::min((256 + base - 1) / base, n / base / 16));
+}
+
 static int items4_of(const md_system *s, int n, int nd)
 {
-    if (nd == 1) return (n + s->launch.build_block - 1) / s->launch.build_block;
+    if (nd == 1) {
+        const int M = single_members(s);
+        return (n + M - 1) / M;
+    }
+    int parts, lanes;
+    build_shape(s, n, nd, parts, lanes);
     int W = s->launch.build_width;
     int nseg = nd <= W + 2 ? 1 : (nd + W - 1) / W;
-    return nd * nd * nseg;
+    return nd * nd * nseg * parts;
 }
 
 static md_status upload_items(md_system *s)
@@ -435,6 +470,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     ba.from_scratch = from_scratch ? 1 : 0;
     ba.width = s->launch.build_width;
     ba.lds_cap = prec == PREC_FP64 ? 1536 : 3072;
+    ba.single_members = single_members(s);
     ba.xcd = s->launch.xcd_remap;
     ba.items_pref = s->items4;
     ba.rep = s->rep;
@@ -464,6 +500,7 @@ static md_status launch_build_main(md_system *s, int slot)
     ba.from_scratch = 0;
     ba.width = s->launch.build_width;
     ba.lds_cap = s->prec == PREC_FP64 ? 1536 : 3072;
+    ba.single_members = single_members(s);
     ba.xcd = s->launch.xcd_remap;
     ba.items_pref = s->items4;
     ba.rep = s->rep;
@@ -580,6 +617,7 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     r.L_lo = (float)(h.L - (double)r.L_hi);
     r.items3 = h.nd * h.nd * h.nd;
     r.items4 = items4_of(s, h.n, h.nd);
+    build_shape(s, h.n, h.nd, r.bparts, r.blanes);
     return r;
 }
 
@@ -793,9 +831,10 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     carve(s, L, s->ws);
     s->launch.step_block = 512;
     s->launch.build_width = 8;
-    s->launch.build_block = 256;
+    s->launch.build_block = 512;
     s->launch.graph_steps = 32;
     s->launch.xcd_remap = 0;
+    s->launch.build_lanes = 0;
     make_tables(s);
     s->slots.assign(L.slots, SlotHost());
     s->parena.reset(L.P);
@@ -1097,53 +1136,67 @@ md_status md_scale_velocities(md_system *s, int32_t slot, double factor)
 md_status md_profile_steps(md_system *s, int64_t n_steps, double *out)
 {
     if (!s || !out) return MD_E_ARG;
-    if (n_steps < 1 || n_steps > (1LL << 24)) return fail(s, MD_E_ARG, "n_steps out of range");
+    if (n_steps < 1 || n_steps > 65536) return fail(s, MD_E_ARG, "n_steps out of range [1, 65536]");
+    const int S = (int)s->lay.slots;
+    const int64_t R = n_steps + 2; // counter rows: before, after each launch
+    int *hn = nullptr;
+    HIPCHK(s, hipHostMalloc((void **)&hn, (size_t)R * S * 4, hipHostMallocDefault));
+    std::vector<hipEvent_t> ev;
+    ev.reserve(3 * (size_t)(n_steps + 1));
+    md_status st = MD_OK;
+    auto cleanup = [&]() {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        (void)hipHostFree(hn);
+    };
+    for (int64_t k = 0; k < 3 * (n_steps + 1) && st == MD_OK; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) st = fail(s, MD_E_HIP, "hipEventCreate failed");
+        else ev.push_back(e);
+    }
+    if (st != MD_OK) { cleanup(); return st; }
     for (auto &h : s->slots)
         if (h.attached) h.target += n_steps;
-    HIPCHK(s, launch_add_targets(s->target, s->ctl[s->parity], (int)s->lay.slots, (int)n_steps, s->stream));
-    hipEvent_t ev[3];
-    for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
-    const int S = (int)s->lay.slots;
-    std::vector<int> nr(S);
-    auto nreb_sum = [&](long long &tot) -> md_status {
-        HIPCHK(s, hipMemcpyAsync(nr.data(), s->nreb, 4 * S, hipMemcpyDeviceToHost, s->stream));
-        HIPCHK(s, hipStreamSynchronize(s->stream));
-        tot = 0;
-        for (int v : nr) tot += v;
-        return MD_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && st == MD_OK) st = fail(s, MD_E_HIP, what);
     };
-    long long prev = 0, cur = 0;
-    md_status st = nreb_sum(prev);
-    double t_step = 0, t_reb = 0, t_reb_hit = 0, n_hit = 0, t_tot = 0;
-    for (int64_t k = 0; k <= n_steps && st == MD_OK; ++k) { // last launch finalises
+    chk(launch_add_targets(s->target, s->ctl[s->parity], S, (int)n_steps, s->stream), "add targets");
+    chk(hipMemcpyAsync(hn, s->nreb, 4 * S, hipMemcpyDeviceToHost, s->stream), "copy counters");
+    for (int64_t k = 0; k <= n_steps && st == MD_OK; ++k) { // the last launch finalises
         const int p = s->parity;
         StepArgs a = step_args(s, p);
-        HIPCHK(s, hipEventRecord(ev[0], s->stream));
-        HIPCHK(s, launch_step(s->prec, a, s->launch.step_block, false, s->stream));
-        HIPCHK(s, hipEventRecord(ev[1], s->stream));
-        st = launch_rebuild(s, p, -1, true);
-        HIPCHK(s, hipEventRecord(ev[2], s->stream));
+        chk(hipEventRecord(ev[3 * k], s->stream), "event");
+        chk(launch_step(s->prec, a, s->launch.step_block, false, s->stream), "step launch");
+        chk(hipEventRecord(ev[3 * k + 1], s->stream), "event");
+        if (st == MD_OK) st = launch_rebuild(s, p, -1, true);
+        chk(hipEventRecord(ev[3 * k + 2], s->stream), "event");
+        chk(hipMemcpyAsync(hn + (k + 1) * S, s->nreb, 4 * S, hipMemcpyDeviceToHost, s->stream), "copy counters");
         s->parity ^= 1;
-        if (st != MD_OK) break;
-        HIPCHK(s, hipEventSynchronize(ev[2]));
+    }
+    chk(hipStreamSynchronize(s->stream), "synchronise");
+    if (st != MD_OK) { cleanup(); return st; }
+    double t_step = 0, t_reb = 0, t_reb_hit = 0, n_hit = 0;
+    auto rowsum = [&](int64_t r) {
+        long long t = 0;
+        for (int q = 0; q < S; ++q) t += hn[r * S + q];
+        return t;
+    };
+    for (int64_t k = 0; k < n_steps && st == MD_OK; ++k) {
         float a01 = 0, a12 = 0;
-        HIPCHK(s, hipEventElapsedTime(&a01, ev[0], ev[1]));
-        HIPCHK(s, hipEventElapsedTime(&a12, ev[1], ev[2]));
-        if ((st = nreb_sum(cur)) != MD_OK) break;
-        if (k == n_steps) break; // the finalising launch is not a step
+        chk(hipEventElapsedTime(&a01, ev[3 * k], ev[3 * k + 1]), "elapsed");
+        chk(hipEventElapsedTime(&a12, ev[3 * k + 1], ev[3 * k + 2]), "elapsed");
         t_step += a01;
         t_reb += a12;
-        t_tot += a01 + a12;
-        if (cur != prev) { t_reb_hit += a12; n_hit += 1; }
-        prev = cur;
+        if (rowsum(k + 1) != rowsum(k)) { t_reb_hit += a12; n_hit += 1; }
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
+    float tot = 0;
+    chk(hipEventElapsedTime(&tot, ev[0], ev[3 * (n_steps - 1) + 2]), "elapsed");
+    cleanup();
     if (st != MD_OK) return st;
     out[0] = t_step / n_steps;
     out[1] = t_reb / n_steps;
     out[2] = n_hit > 0 ? t_reb_hit / n_hit : 0.0;
     out[3] = n_hit;
-    out[4] = t_tot;
+    out[4] = tot;
     return MD_OK;
 }
 
@@ -1408,6 +1461,8 @@ md_status md_set_launch(md_system *s, const md_launch *in)
     if (l.step_block < 64 || l.step_block > 1024 || l.step_block % 64) return fail(s, MD_E_ARG, "bad step_block");
     if (l.build_block < 64 || l.build_block > 1024 || l.build_block % 64) return fail(s, MD_E_ARG, "bad build_block");
     if (l.build_width < 1 || l.build_width > 16) return fail(s, MD_E_ARG, "bad build_width");
+    if (l.build_lanes < 0 || l.build_lanes > 64 || (l.build_lanes & (l.build_lanes - 1)))
+        return fail(s, MD_E_ARG, "bad build_lanes");
     if (l.graph_steps != 0 && (l.graph_steps < 2 || l.graph_steps > 256 || l.graph_steps % 2))
         return fail(s, MD_E_ARG, "bad graph_steps");
     drop_graphs(s);

@@ -708,65 +708,91 @@ __global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
 }
 
 // ------------------------------------------------------------ k_permute
-// One wave per new cell: stable scatter of its members into scratch.
+// One wave per new cell: stable scatter of its members into scratch.  Each
+// pass first loads every member it moves, then folds and stores them: on
+// this hardware one counter tracks loads and stores alike, so a load issued
+// after a store would also wait for that store.
+template <int P> struct Moved {
+    uint4 st[Traits<P>::NW];
+    int4 meta;
+    uint4 snap; // the snapshot (fixed point), or its second word (double)
+};
+
 template <int P>
-__device__ __forceinline__ void fold_and_copy(const PermArgs &a, const RepDev &rp, int q, int dst)
+__device__ __forceinline__ void move_load(const PermArgs &a, int q, Moved<P> &mv)
+{
+    constexpr int NW = Traits<P>::NW, NS = Traits<P>::NS;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) mv.st[w] = a.A.st[w][q];
+    mv.meta = a.A.meta[q];
+    mv.snap = NS == 1 ? a.snap[q] : a.snap[(size_t)a.A.P + q];
+}
+
+__device__ __forceinline__ float4 u4_as_f4(uint4 u)
+{
+    return make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
+}
+__device__ __forceinline__ uint4 f4_as_u4(float4 f)
+{
+    return make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w));
+}
+
+// Fold the member's position into [0, L) (counting the image shift in its
+// meta word) and store it at scratch slot dst.
+template <int P>
+__device__ __forceinline__ void move_store(const PermArgs &a, const RepDev &rp, const Moved<P> &mv, int dst)
 {
     constexpr int NS = Traits<P>::NS;
-    const KArena &A = a.A;
-    int4 m = ((const int4 *)A.meta)[q];
+    int4 m = mv.meta;
     int ix = 0, iy = 0, iz = 0;
+    int *im[3] = {&ix, &iy, &iz};
     if constexpr (P == PREC_FP32) {
-        float4 p = ((const float4 *)A.st[0])[q];
+        float4 p = u4_as_f4(mv.st[0]);
         float *c[3] = {&p.x, &p.y, &p.z};
-        int *im[3] = {&ix, &iy, &iz};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (*c[d] < 0.0f) { *c[d] += rp.Lf; *im[d] -= 1; }
             if (*c[d] >= rp.Lf) { *c[d] -= rp.Lf; *im[d] += 1; }
         }
-        ((float4 *)a.sc_st[0])[dst] = p;
-        a.sc_st[1][dst] = A.st[1][q];
+        a.sc_st[0][dst] = f4_as_u4(p);
+        a.sc_st[1][dst] = mv.st[1];
     } else if constexpr (P == PREC_DS) {
-        float4 w0 = ((const float4 *)A.st[0])[q], w1 = ((const float4 *)A.st[1])[q];
+        const float4 w0 = u4_as_f4(mv.st[0]), w1 = u4_as_f4(mv.st[1]);
         dsf x = {w0.x, w0.w}, y = {w0.y, w1.x}, z = {w0.z, w1.y};
-        dsf L = {rp.L_hi, rp.L_lo};
+        const dsf L = {rp.L_hi, rp.L_lo};
         dsf *c[3] = {&x, &y, &z};
-        int *im[3] = {&ix, &iy, &iz};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (c[d]->hi < 0.0f) { *c[d] = ds_add(*c[d], L); *im[d] -= 1; }
-            dsf t = ds_sub(*c[d], L);
+            const dsf t = ds_sub(*c[d], L);
             if (t.hi >= 0.0f) { *c[d] = t; *im[d] += 1; }
         }
-        ((float4 *)a.sc_st[0])[dst] = make_float4(x.hi, y.hi, z.hi, x.lo);
-        ((float4 *)a.sc_st[1])[dst] = make_float4(y.lo, z.lo, w1.z, w1.w);
-        a.sc_st[2][dst] = A.st[2][q];
+        a.sc_st[0][dst] = f4_as_u4(make_float4(x.hi, y.hi, z.hi, x.lo));
+        a.sc_st[1][dst] = f4_as_u4(make_float4(y.lo, z.lo, w1.z, w1.w));
+        a.sc_st[2][dst] = mv.st[2];
     } else {
-        double2 w0 = ((const double2 *)A.st[0])[q], w1 = ((const double2 *)A.st[1])[q];
-        double *c[3] = {&w0.x, &w0.y, &w1.x};
-        int *im[3] = {&ix, &iy, &iz};
+        double x, y, z, w;
+        u4_to_dbl2(mv.st[0], x, y);
+        u4_to_dbl2(mv.st[1], z, w);
+        double *c[3] = {&x, &y, &z};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (*c[d] < 0.0) { *c[d] += rp.L; *im[d] -= 1; }
             if (*c[d] >= rp.L) { *c[d] -= rp.L; *im[d] += 1; }
         }
-        ((double2 *)a.sc_st[0])[dst] = w0;
-        ((double2 *)a.sc_st[1])[dst] = w1;
-        a.sc_st[2][dst] = A.st[2][q];
+        a.sc_st[0][dst] = dbl2_to_u4(x, y);
+        a.sc_st[1][dst] = dbl2_to_u4(z, w);
+        a.sc_st[2][dst] = mv.st[2];
+        if constexpr (NS == 2) { // the double snapshot, from the folded state
+            double zz, ww;
+            u4_to_dbl2(mv.snap, zz, ww);
+            a.sc_snap[dst] = dbl2_to_u4(x, y);
+            a.sc_snap[(size_t)a.A.P + dst] = dbl2_to_u4(z, ww);
+        }
     }
     m.x += ix; m.y += iy; m.z += iz;
-    ((int4 *)a.sc_meta)[dst] = m;
-    if constexpr (NS == 1) {
-        a.sc_snap[dst] = a.snap[q];
-    } else {
-        // rebuild the double snapshot from the folded state
-        double2 w0 = ((const double2 *)a.sc_st[0])[dst], w1 = ((const double2 *)a.sc_st[1])[dst];
-        double zz, ww;
-        u4_to_dbl2(a.snap[(size_t)A.P + q], zz, ww);
-        a.sc_snap[dst] = dbl2_to_u4(w0.x, w0.y);
-        a.sc_snap[(size_t)A.P + dst] = dbl2_to_u4(w1.x, ww);
-    }
+    a.sc_meta[dst] = m;
+    if constexpr (NS == 1) a.sc_snap[dst] = mv.snap;
 }
 
 template <int P>
@@ -833,25 +859,30 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
         __builtin_amdgcn_wave_barrier();
         const int tot = pref[wv][nold];
         int run = 0;
-        for (int b = 0; b < tot; b += 256) {
-            int q[4];
-            bool m[4];
+        int r = 0; // old cell of the lane's current candidate (only moves forward)
+        constexpr int U = 4; // candidates per lane per pass
+        for (int b = 0; b < tot; b += 64 * U) {
+            int q[U];
+            bool m[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int e = b + 64 * u + lane;
                 q[u] = -1;
                 if (e < tot) {
-                    int r = 0;
                     while (r + 1 < nold && pref[wv][r + 1] <= e) ++r;
                     q[u] = pst[wv][r] + (e - pref[wv][r]);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) m[u] = q[u] >= 0 && (nd == 1 || in_cell<P>(a, rp, q[u], c));
+            for (int u = 0; u < U; ++u) m[u] = q[u] >= 0 && (nd == 1 || in_cell<P>(a, rp, q[u], c));
+            Moved<P> mv[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u)
+                if (m[u]) move_load<P>(a, q[u], mv[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 const unsigned long long bal = __ballot(m[u]);
-                if (m[u]) fold_and_copy<P>(a, rp, q[u], dst0 + run + __popcll(bal & ((1ull << lane) - 1ull)));
+                if (m[u]) move_store<P>(a, rp, mv[u], dst0 + run + __popcll(bal & ((1ull << lane) - 1ull)));
                 run += __popcll(bal);
             }
         }
@@ -874,6 +905,7 @@ struct BuildTabs {
     int start[BUILD_TAB]; // LDS start of staged cell (global start when not staged)
     int cnt[BUILD_TAB];
     int glob[BUILD_TAB];  // global start of the cell
+    int4 pk[BUILD_TAB];   // (start, cnt, glob) of each staged cell, for the grouped scan
     int run_lds[19], run_glob[19];
     int nruns, total, fits, NX;
 };
@@ -989,7 +1021,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             for (int e = 0; e < n && pad < 0; ++e)
                 if (!test(e, st) && g0 + e != i) pad = g0 + e;
         }
-        for (int k = 0; k < 9 * NX && pad < 0; ++k) {
+        for (int k = 0; k < (nd == 1 ? 1 : 9 * NX) && pad < 0; ++k) {
             const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
             for (int e = 0; e < n && pad < 0; ++e)
                 if (!test(e, st) && g0 + e != i) pad = g0 + e;
@@ -1000,6 +1032,136 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
     }
     A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
     if (cnt > A.cap) atomicOr(a.status + s, 1);
+}
+
+// The same list, built by a group of G lanes (G a power of two <= 64, the
+// group's lanes adjacent in one wave): the member's candidates, concatenated
+// in the canonical cell order, are tested G at a time, one per lane, and the
+// accepted ones are stored at the running count plus their rank among the
+// group's accepted lanes (ballot + popcount), i.e. in exactly the order of
+// the one-lane scan.  Splits one member's dependent candidate chain G ways,
+// which is what bounds the build of small replicas.
+template <int P, bool FROM_LDS>
+__device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
+                                                 const BuildTabs &T, bool full, const uint4 *cand, int s,
+                                                 int nd, int G, int gl, unsigned long long gmask,
+                                                 unsigned long long below)
+{
+    constexpr int NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    const size_t P_ = (size_t)A.P;
+    const int NX = T.NX;
+    uint4 xi = a.src_x[i];
+    double xd = 0, yd = 0, zd = 0, wd = 0;
+    uint32_t meta;
+    if (NS == 2) {
+        u4_to_dbl2(xi, xd, yd);
+        u4_to_dbl2(a.src_x[P_ + i], zd, wd);
+        meta = meta_of_bits(wd);
+    } else meta = xi.w;
+    const int si = (int)(meta & SPECIES_MASK);
+    float rl2s0, rl2s1;
+    double rl2d0 = a.pp.rl2d[si * 2], rl2d1 = a.pp.rl2d[si * 2 + 1];
+    {
+        const double u = (double)rp.sc;
+        rl2s0 = (float)(rl2d0 / (u * u));
+        rl2s1 = (float)(rl2d1 / (u * u));
+    }
+    const int cap = A.cap;
+    int *col = A.nbr_w + 4 * (size_t)i;
+    const size_t row_stride = 4 * P_;
+    auto test = [&](int e, int st) -> bool {
+        if (NS == 2) {
+            double xj, yj, zj, wj;
+            if (FROM_LDS) {
+                u4_to_dbl2(cand[2 * (st + e)], xj, yj);
+                u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
+            } else {
+                u4_to_dbl2(a.src_x[st + e], xj, yj);
+                u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
+            }
+            double dx = xd - xj, dy = yd - yj, dz = zd - zj;
+            dx -= rp.L * rint(dx * rp.invL);
+            dy -= rp.L * rint(dy * rp.invL);
+            dz -= rp.L * rint(dz * rp.invL);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
+        }
+        const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+        const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
+                    dz = (float)(int)(xi.z - xj.z);
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
+    };
+    // one cell's candidates, 4G at a time: lane gl tests e = b + u G + gl
+    // (u = 0..3, independent loads in flight); the ballots are taken in u
+    // order, which is ascending e
+    int cnt = 0;
+    auto scan_cell = [&](int k) {
+        const int4 c = T.pk[k]; // (start, cnt, glob)
+        for (int b = 0; b < c.y; b += 4 * G) {
+            bool acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = b + u * G + gl;
+                acc[u] = e < c.y && test(e, c.x) && c.z + e != i;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned long long m = __ballot(acc[u]) & gmask;
+                if (acc[u]) {
+                    const int k2 = cnt + __popcll(m & below);
+                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = c.z + b + u * G + gl;
+                }
+                cnt += __popcll(m);
+            }
+        }
+    };
+    // visiting order: own cell, then +o, -o for q = 14..26 of the
+    // (dz, dy, dx) enumeration of the 27 offsets
+    auto cell_k = [&](int dx, int dy, int dz) {
+        int lx = lx_m + dx;
+        if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
+        return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
+    };
+    int last_cell = 0;
+    if (nd == 1) {
+        scan_cell(0);
+    } else {
+        scan_cell(cell_k(0, 0, 0));
+        for (int q = 14; q < 27; ++q) {
+            const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
+            scan_cell(cell_k(dx, dy, dz));
+            last_cell = cell_k(-dx, -dy, -dz);
+            scan_cell(last_cell);
+        }
+    }
+    // pad to a multiple of 8, as in the one-lane build: the first rejected
+    // candidate of the last visited cell, else (rare) of any staged cell
+    if (cnt & 7) {
+        int pad = -1;
+        const int4 cl = T.pk[last_cell];
+        for (int b = 0; b < cl.y; b += G) {
+            const int e = b + gl;
+            const bool r = e < cl.y && !test(e, cl.x) && cl.z + e != i;
+            const unsigned long long m = __ballot(r) & gmask;
+            if (m) { pad = cl.z + b + (__ffsll(m) - 1) - (__ffsll(gmask) - 1); break; }
+        }
+        if (gl == 0) {
+            for (int k = 0; k < (nd == 1 ? 1 : 9 * NX) && pad < 0; ++k) {
+                const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+                for (int e = 0; e < n && pad < 0; ++e)
+                    if (!test(e, st) && g0 + e != i) pad = g0 + e;
+            }
+            if (pad < 0) atomicOr(a.status + s, 8);
+            for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
+                col[(size_t)(k >> 2) * row_stride + (k & 3)] = pad < 0 ? i : pad;
+        }
+    }
+    if (gl == 0) {
+        A.nbr_cnt_w[i] = cnt < cap ? cnt : cap;
+        if (cnt > cap) atomicOr(a.status + s, 1);
+    }
 }
 
 template <int P>
@@ -1036,8 +1198,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
         int m0, m1, NX = 1, x0 = 0, x1 = 1, rowbase = 0;
         bool full = true;
         if (nd == 1) {
-            m0 = rp.off + item * B;
-            m1 = min(m0 + B, rp.off + rp.n);
+            m0 = rp.off + item * a.single_members;
+            m1 = min(m0 + a.single_members, rp.off + rp.n);
             if (t == 0) {
                 T.glob[0] = rp.off;
                 T.cnt[0] = rp.n;
@@ -1054,15 +1216,19 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             const int W = a.width;
             full = nd <= W + 2;
             const int nseg = full ? 1 : (nd + W - 1) / W;
-            const int seg = item % nseg, row = item / nseg;
+            const int part = item % rp.bparts, segitem = item / rp.bparts;
+            const int seg = segitem % nseg, row = segitem / nseg;
             const int cy = row % nd, cz = row / nd;
             x0 = full ? 0 : (seg * nd) / nseg;           // balanced segments
             x1 = full ? nd : ((seg + 1) * nd) / nseg;
             NX = full ? nd : x1 - x0 + 2;
             rowbase = nd * (cy + nd * cz);
-            m0 = cs[rowbase + x0];
-            m1 = cs[rowbase + x1];
-            if (a.from_scratch) { // retire the old cell starts of this segment
+            {   // this item's share of the segment's members
+                const int s0 = cs[rowbase + x0], ms = cs[rowbase + x1] - s0;
+                m0 = s0 + (int)(((long long)part * ms) / rp.bparts);
+                m1 = s0 + (int)(((long long)(part + 1) * ms) / rp.bparts);
+            }
+            if (a.from_scratch && part == 0) { // retire the old cell starts of this segment
                 for (int k = x0 + t; k < x1; k += B) a.cs[rp.coff + rowbase + k] = cs[rowbase + k];
                 if (t == 0 && rowbase + x1 == nd * nd * nd)
                     a.cs[rp.coff + nd * nd * nd] = cs[nd * nd * nd];
@@ -1114,11 +1280,12 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
                 for (int k = t; k < 9 * NX; k += B) T.start[k] = T.glob[k];
         }
         __syncthreads();
+        for (int k = t; k < (nd == 1 ? 1 : 9 * NX); k += B) T.pk[k] = make_int4(T.start[k], T.cnt[k], T.glob[k], 0);
         const bool fits = T.fits != 0;
         if (fits) { // stage: element e lies in the last run whose LDS start is <= e
             const int tot = T.total, nr = T.nruns;
+            int r = 0; // only moves forward as e grows
             for (int e = t; e < tot; e += B) {
-                int r = 0;
                 while (r + 1 < nr && T.run_lds[r + 1] <= e) ++r;
                 const int g = T.run_glob[r] + (e - T.run_lds[r]);
                 if (NS == 2) {
@@ -1128,17 +1295,40 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             }
         }
         __syncthreads();
-        for (int i = m0 + t; i < m1; i += B) {
-            int lx_m = 0;
-            if (nd > 1) { // the member's cell: own-row staged cell whose range holds i
-                int lx = full ? 0 : 1;
-                const int le = full ? NX - 1 : NX - 2;
-                while (lx < le && T.glob[4 * NX + lx + 1] <= i) ++lx;
-                lx_m = lx;
+        // the member's cell: own-row staged cell whose range holds i
+        auto member_cell = [&](int i) {
+            if (nd == 1) return 0;
+            int lx = full ? 0 : 1;
+            const int le = full ? NX - 1 : NX - 2;
+            while (lx < le && T.glob[4 * NX + lx + 1] <= i) ++lx;
+            return lx;
+        };
+        // lanes per member: the replica's (fixed by the launch, or one lane
+        // for large replicas), else the largest power of two that still
+        // gives every member of this work item its own group
+        int G = rp.blanes;
+        if (G == 0) {
+            G = 1;
+            while (G < 64 && (2 * G) * (m1 - m0) <= B) G *= 2;
+        }
+        if (G == 1) {
+            for (int i = m0 + t; i < m1; i += B) {
+                const int lx_m = member_cell(i);
+                if (fits) build_member<P, true>(a, rp, i, lx_m, T, full, cand, s, nd);
+                else build_member<P, false>(a, rp, i, lx_m, T, full, cand, s, nd);
+                copy_back<P>(a, i);
             }
-            if (fits) build_member<P, true>(a, rp, i, lx_m, T, full, cand, s, nd);
-            else build_member<P, false>(a, rp, i, lx_m, T, full, cand, s, nd);
-            copy_back<P>(a, i);
+        } else {
+            const int lane = t & 63, gl = t & (G - 1);
+            const unsigned long long gmask =
+                G == 64 ? ~0ull : ((1ull << G) - 1ull) << (lane & ~(G - 1));
+            const unsigned long long below = (1ull << lane) - 1ull;
+            for (int i = m0 + t / G; i < m1; i += B / G) {
+                const int lx_m = member_cell(i);
+                if (fits) build_member_grp<P, true>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
+                else build_member_grp<P, false>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
+                if (gl == 0) copy_back<P>(a, i);
+            }
         }
         __syncthreads();
     });

@@ -74,6 +74,7 @@ struct PermArgs {
 struct BuildArgs {
     KArena A;
     int max_slots, force_slot, from_scratch, width, lds_cap, xcd;
+    int single_members; // members per work item of a single-cell replica
     const int *items_pref;
     const RepDev *rep;
     const int *need;

@@ -44,6 +44,8 @@ struct RepDev {
     float Lf;     // L rounded to float (FP32 wrap)
     float L_hi, L_lo; // L as double-single
     int items3, items4; // work items of the sort and list-build kernels
+    int bparts;   // list-build work items per row segment (its members split evenly)
+    int blanes;   // lanes building one member's list; 0 = chosen per work item
 };
 
 // Control word of a slot: x = completed steps, y = 1 if velocities are at a

@@ -72,11 +72,12 @@ class MdObs(ctypes.Structure):
 class MdLaunch(ctypes.Structure):
     _fields_ = [("step_block", ctypes.c_int32), ("build_width", ctypes.c_int32),
                 ("build_block", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("xcd_remap", ctypes.c_int32), ("build_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k in
-                ("step_block", "build_width", "build_block", "graph_steps", "xcd_remap")}
+                ("step_block", "build_width", "build_block", "graph_steps", "xcd_remap", "build_lanes")}
 
 
 class MdError(RuntimeError):

@@ -1,14 +1,37 @@
-"""Summaries of rocprofv3 CSV output (kernel statistics and per-kernel PMC
-averages) for the profiles/ notes.
+"""Summaries of rocprofv3 CSV output (kernel statistics, per-kernel PMC
+averages, and calibrated HBM traffic per launch) for the profiles/ notes.
 
-  python -m paper_0912_3824_amd.profiling stats  <dir-with-*_kernel_stats.csv>
-  python -m paper_0912_3824_amd.profiling pmc    <dir-with-*_counter_collection.csv>
+  python -m paper_0912_3824_amd.profiling stats   <dir-with-*_kernel_stats.csv>
+  python -m paper_0912_3824_amd.profiling pmc     <dir-with-*_counter_collection.csv>
+  python -m paper_0912_3824_amd.profiling traffic <fetch-dir> <write-dir> --kernel REGEX
+        [--copy-bytes 268435456] [--json OUT] [--command "..."]
+
+The traffic mode scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the
+chosen kernel by what the same counters read for a plain device copy of
+--copy-bytes bytes (the largest-grid __amd_rocclr_copyBuffer dispatch in the
+same runs), so that the result is in true bytes moved to and from HBM.
 """
+import argparse
 import csv
 import glob
+import hashlib
+import json
 import os
+import re
 import sys
 from collections import defaultdict
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device sources: counter summaries taken on other sources
+    are stale."""
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "md_dev.hpp", "ds.hpp", "kernels.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _find(d, suffix):
@@ -31,20 +54,79 @@ def kernel_stats(d):
     return "\n".join(out)
 
 
-def pmc(d):
+def _counters(d):
     acc = defaultdict(lambda: defaultdict(list))
     for f in _find(d, "counter_collection.csv"):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                key = (r["Kernel_Name"], r.get("Grid_Size", ""))
+                key = (r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0))
                 acc[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return acc
+
+
+def pmc(d):
     out = ["kernel | grid | counter | dispatches | mean per dispatch"]
-    for (k, g), cs in sorted(acc.items()):
+    for (k, g), cs in sorted(_counters(d).items()):
         for c, v in sorted(cs.items()):
             out.append(f"{k} | {g} | {c} | {len(v)} | {sum(v) / len(v):.6g}")
     return "\n".join(out)
 
 
+def _mean_of(acc, counter, pred):
+    vals = []
+    for (k, g), cs in acc.items():
+        if pred(k, g) and counter in cs:
+            vals += cs[counter]
+    if not vals:
+        raise SystemExit(f"no {counter} samples for the selected kernel")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(fetch_dir, write_dir, kernel_regex, copy_bytes):
+    rx = re.compile(kernel_regex)
+    fa, wa = _counters(fetch_dir), _counters(write_dir)
+
+    def copy_pred(acc):
+        grids = [g for (k, g) in acc if "copyBuffer" in k]
+        if not grids:
+            raise SystemExit("no copy-kernel dispatch to calibrate against")
+        gmax = max(grids)
+        return lambda k, g: "copyBuffer" in k and g == gmax
+
+    cf, _ = _mean_of(fa, "FETCH_SIZE", copy_pred(fa))
+    cw, _ = _mean_of(wa, "WRITE_SIZE", copy_pred(wa))
+    fetch_scale = copy_bytes / (cf * 1024.0)
+    write_scale = copy_bytes / (cw * 1024.0)
+    kf, nf = _mean_of(fa, "FETCH_SIZE", lambda k, g: bool(rx.search(k)))
+    kw, nw = _mean_of(wa, "WRITE_SIZE", lambda k, g: bool(rx.search(k)))
+    fetched = kf * 1024.0 * fetch_scale
+    written = kw * 1024.0 * write_scale
+    return {"kernel_regex": kernel_regex, "kernel_hash": kernel_source_hash(),
+            "dispatches": [nf, nw],
+            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
+            "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+            "fetch_scale": fetch_scale, "write_scale": write_scale,
+            "hbm_read_bytes_per_launch": fetched, "hbm_write_bytes_per_launch": written,
+            "hbm_bytes_per_launch": fetched + written}
+
+
 if __name__ == "__main__":
-    mode, d = sys.argv[1], sys.argv[2]
-    print(kernel_stats(d) if mode == "stats" else pmc(d))
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["stats", "pmc", "traffic"])
+    ap.add_argument("dirs", nargs="+")
+    ap.add_argument("--kernel", default=r"k_step<")
+    ap.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
+    ap.add_argument("--json", default=None)
+    ap.add_argument("--command", default="")
+    a = ap.parse_args()
+    if a.mode == "stats":
+        print(kernel_stats(a.dirs[0]))
+    elif a.mode == "pmc":
+        print(pmc(a.dirs[0]))
+    else:
+        t = traffic(a.dirs[0], a.dirs[1], a.kernel, a.copy_bytes)
+        t["command"] = a.command
+        if a.json:
+            with open(a.json, "w") as fh:
+                json.dump(t, fh, indent=1)
+        print(json.dumps(t, indent=1))

@@ -1,8 +1,8 @@
 """Autotuner of libmdx launch shapes.
 
 The knobs (md_launch: block size of the fused step kernel, cells per LDS row
-segment and block size of the list build, steps per captured hipGraph, XCD-
-aware tile mapping) change no result bit: lists are in a canonical order and
+segment, block size and lanes per member of the list build, steps per
+captured hipGraph, XCD-aware tile mapping) change no result bit: lists are in a canonical order and
 every particle sums its own list sequentially.  The tuner therefore times
 candidate shapes on the live pool, from a saved checkpoint so that every
 candidate advances the same trajectory, and keeps the fastest.  Results are
@@ -20,9 +20,10 @@ from typing import Dict, List, Optional
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 SPACE = {
-    "step_block": [64, 128, 256, 512],
-    "build_width": [4, 8, 12],
-    "build_block": [128, 256, 512],
+    "step_block": [256, 512],
+    "build_width": [4, 8],
+    "build_block": [256, 512],
+    "build_lanes": [0, 16],
     "graph_steps": [32],
     "xcd_remap": [0, 1],
 }

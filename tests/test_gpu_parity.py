@@ -46,13 +46,14 @@ def test_forces_match_oracle(prec, n, lpp):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n,width", [(500, 4), (3001, 1), (3001, 4), (12007, 2)])
-def test_neighbour_lists_match_oracle(prec, n, width):
+@pytest.mark.parametrize("n,width,lanes", [(500, 4, 0), (500, 4, 1), (3001, 1, 0), (3001, 4, 1),
+                                           (3001, 4, 64), (12007, 2, 0), (12007, 8, 1), (12007, 8, 2)])
+def test_neighbour_lists_match_oracle(prec, n, width, lanes):
     s = _ka(n)
-    say("lists", prec, n, width)
+    say("lists", prec, n, "width", width, "lanes", lanes)
     pool = pool_for([s], prec)
-    if width != 4:
-        pool.set_launch(build_width=width)
+    if (width, lanes) != (4, 0):
+        pool.set_launch(build_width=width, build_lanes=lanes)
         pool.rebuild_neighbours()
     pos, vel, img = pool.get_state(0)
     cnt, ids = pool.neighbours(0, cap=256)
@@ -68,6 +69,27 @@ def test_neighbour_lists_match_oracle(prec, n, width):
         assert len(got) == cnt[i]  # no duplicates
     say("  ambiguous-band particles differing:", bad)
     assert bad <= max(1, n // 10000)
+    pool.close()
+
+
+@pytest.mark.parametrize("prec,n", [("ds", 500), ("ds", 3001), ("ds", 12007), ("ds", 60000),
+                                    ("fp64", 500), ("fp64", 3001), ("fp64", 12007)])
+def test_list_build_lanes_give_identical_lists(prec, n):
+    """One lane per member and groups of 2..64 lanes per member, with row
+    segments built by one or several work items (several block sizes and
+    row widths), build the same lists, entry by entry."""
+    s = _ka(n)
+    pool = pool_for([s], prec)
+    ref = None
+    for lanes, block, width in [(1, 256, 4), (2, 256, 4), (4, 512, 1), (8, 1024, 2), (16, 256, 8),
+                                (32, 64, 4), (64, 1024, 4), (0, 512, 8), (0, 64, 1)]:
+        pool.set_launch(build_lanes=lanes, build_block=block, build_width=width)
+        pool.rebuild_neighbours()
+        cnt, ids = pool.neighbours(0, cap=256)
+        say("lanes", prec, n, lanes, block, width, "entries", int(cnt.sum()))
+        if ref is None:
+            ref = (cnt, ids)
+        assert np.array_equal(cnt, ref[0]) and np.array_equal(ids, ref[1]), (lanes, block, width)
     pool.close()
 
 

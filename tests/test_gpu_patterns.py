@@ -58,7 +58,10 @@ def test_graph_eager_shapes_and_split_calls_are_bitwise_equal():
                          (dict(graph_steps=0), [400]),
                          (dict(graph_steps=8, step_block=64, build_width=2, build_block=128), [400]),
                          (dict(graph_steps=32, step_block=1024, xcd_remap=1, build_width=16), [150, 1, 249]),
-                         (dict(graph_steps=2), [100, 100, 200])]:
+                         (dict(graph_steps=2), [100, 100, 200]),
+                         (dict(build_lanes=1, build_block=512), [400]),
+                         (dict(build_lanes=64, build_block=1024, build_width=1), [200, 200]),
+                         (dict(build_lanes=4, build_block=128, build_width=3), [400])]:
         pool = pool_for([s], "ds")
         pool.set_launch(**shape)
         for c in calls:

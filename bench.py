@@ -94,25 +94,28 @@ def equilibrate(pool, systems, steps: int, every: int = 100):
                 pool.scale_velocities(slot, math.sqrt(s.temperature / t))
 
 
-def cpu_baseline(system, budget_s: float = 12.0):
+def cpu_baseline(system, budget_s: float = 15.0):
     """The FP64 oracle (brute force) timed on a bounded sample of the same
-    workload: forces on m particles of the system, m sized for ~budget_s."""
+    workload: forces on m randomly chosen particles of the system, m grown
+    until one timed call takes about budget_s (bounded to ~2 budgets of CPU
+    time in total)."""
     import numpy as np
     from oracle import oracle as O
     O.build(force=False)
     rng = np.random.default_rng(1)
     cores = len(os.sched_getaffinity(0))
     n = system.n
-    m0 = 64 if n > 100000 else 512
-    sel = rng.choice(n, size=min(m0, n), replace=False).astype(np.int32)
-    t0 = time.perf_counter()
-    O.forces(system.pos, system.box, system.species, system.table, sel)
-    dt0 = time.perf_counter() - t0
-    m = int(min(n, max(m0, m0 * budget_s / max(dt0, 1e-6))))
-    sel = rng.choice(n, size=m, replace=False).astype(np.int32)
-    t0 = time.perf_counter()
-    O.forces(system.pos, system.box, system.species, system.table, sel)
-    dt = time.perf_counter() - t0
+    m = min(n, 256 if n > 100000 else 2048)
+    spent = 0.0
+    while True:
+        sel = rng.choice(n, size=m, replace=False).astype(np.int32)
+        t0 = time.perf_counter()
+        O.forces(system.pos, system.box, system.species, system.table, sel)
+        dt = time.perf_counter() - t0
+        spent += dt
+        if m >= n or dt >= 0.6 * budget_s or spent + 2 * dt > 2 * budget_s:
+            break
+        m = int(min(n, m * min(8.0, max(1.5, budget_s / max(dt, 1e-3)))))
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {"value": m / dt, "unit": "particle-steps/s", "cores": min(threads, cores),
             "kind": "oracle",

@@ -566,7 +566,7 @@ static md_status run_launches(md_system *s, int64_t n)
     return MD_OK;
 }
 
-// Small control kernels live in kernels.hip; declare the launchers here.
+// Small control kernels live in aux_kernels.hip; declare the launchers here.
 hipError_t launch_add_targets(int *target, const Ctl *ctl, int max_slots, int delta, hipStream_t s);
 hipError_t launch_poke(int *p, int v, hipStream_t s);
 

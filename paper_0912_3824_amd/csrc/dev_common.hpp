@@ -1,0 +1,171 @@
+#pragma once
+// Device code shared by the HIP kernels of libmdx for gfx950 (wave64):
+// work-item walkers, word conversions and the per-precision particle state.
+//
+// Overview of the kernels (step.hip, rebuild.hip, aux_kernels.hip):
+//
+// One MD step (Sec. 2.2, velocity Verlet with Verlet lists) is one fused
+// launch of k_step plus three rebuild kernels that exit at once unless the
+// replica's maximum displacement since its last list build exceeded skin/2:
+//
+//   k_step<P>    per particle: force over its Verlet list (FP32 pair term,
+//                sum in the precision P), second half-kick of step n (full-
+//                step velocity), first half-kick of step n+1, drift,
+//                fixed-point snapshot of the new position, displacement test
+//                against the list's reference position, and the count of the
+//                particle's new cell (for the sort, Sec. 2.2 cell binning).
+//   k_scan       per replica: exclusive scan of the cell counts -> cell starts.
+//   k_permute<P> per cell (one wave): stable counting-sort scatter.  Members
+//                of a new cell come from the 27 surrounding old cells (a
+//                particle moves less than one cell between builds); a ballot
+//                over them in old slot order gives each its new slot.  The
+//                whole particle record is gathered into the scratch arena,
+//                positions folded back into the box.
+//   k_build<P>   per row segment of cells (one workgroup): the segment's
+//                27-cell neighbourhood is staged in LDS, every member scans
+//                its own cell and then the 13 opposite cell pairs (Sec. 4.1)
+//                and writes its list column-major; the sorted record is
+//                copied back from scratch.
+//
+// Bitwise determinism: lists are in a canonical order (own cell, then +o/-o
+// pairs, slot order inside a cell), the sort is stable, each particle sums
+// its own list sequentially, and no floating-point atomics are used.  The
+// result for a replica therefore does not depend on launch shapes or on
+// other replicas in the pool.
+#include "md_dev.hpp"
+#include "kernels.hpp"
+
+#define LAUNCH_CHECK() return hipGetLastError()
+
+// --------------------------------------------------------------- utilities
+__device__ __forceinline__ int remap_block(int b, int nblk, int on)
+{
+    // Consecutive tiles to one XCD: workgroups are dealt round-robin over
+    // the 8 XCDs, so block b runs on XCD b % 8.
+    if (!on) return b;
+    int per = nblk >> 3;
+    if (b < (per << 3)) return (b & 7) * per + (b >> 3);
+    return b;
+}
+
+__device__ __forceinline__ int slot_of_meta(uint32_t w) { return (int)(w >> SLOT_SHIFT); }
+
+__device__ __forceinline__ int find_item_slot(const int *pref, int nslots, int item)
+{
+    // pref[0..nslots] non-decreasing; find s with pref[s] <= item < pref[s+1]
+    int lo = 0, hi = nslots;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pref[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Work-item walk of the rebuild kernels.  A step's rebuild (force_slot -1)
+// visits only the items of the slots on the rebuild list written by k_step;
+// a host-forced rebuild visits every item and filters by slot.  `unit` is
+// this worker's index among `nunits` workers; visit(slot, item) is called for
+// each item assigned to it.  Consecutive slots start on different workers so
+// that small replicas spread over the grid.
+template <class F>
+__device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
+                                          int max_slots, int force_slot, const Ctl *ctl, int which,
+                                          int unit, int nunits, F visit);
+
+__device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *need, const Ctl *ctl)
+{
+    if (force_slot == -1) return need && need[s] != 0;
+    if (force_slot == -2) return ctl[s].z != 0;
+    return s == force_slot;
+}
+
+template <class F>
+__device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
+                                          int max_slots, int force_slot, const Ctl *ctl, int which,
+                                          int unit, int nunits, F visit)
+{
+    if (force_slot == -1) {
+        const int cnt = rlist[0];
+        int cum = 0;
+        for (int li = 0; li < cnt; ++li) {
+            const int s = rlist[1 + li];
+            const int items = which == 3 ? rep[s].items3 : rep[s].items4;
+            int first = unit - cum % nunits;
+            first += first < 0 ? nunits : 0;
+            for (int it = first; it < items; it += nunits) visit(s, it);
+            cum += items;
+        }
+        return;
+    }
+    const int total = items_pref[max_slots];
+    for (int it = unit; it < total; it += nunits) {
+        const int s = find_item_slot(items_pref, max_slots, it);
+        if (!slot_selected(s, force_slot, nullptr, ctl)) continue;
+        visit(s, it - items_pref[s]);
+    }
+}
+
+__device__ __forceinline__ uint4 dbl2_to_u4(double a, double b)
+{
+    uint4 u;
+    unsigned long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    u.x = (uint32_t)x; u.y = (uint32_t)(x >> 32); u.z = (uint32_t)y; u.w = (uint32_t)(y >> 32);
+    return u;
+}
+__device__ __forceinline__ void u4_to_dbl2(uint4 u, double &a, double &b)
+{
+    a = __longlong_as_double(((unsigned long long)u.y << 32) | u.x);
+    b = __longlong_as_double(((unsigned long long)u.w << 32) | u.z);
+}
+
+// ------------------------------------------------------- per-precision state
+template <int P> struct State;
+
+template <> struct State<PREC_FP32> {
+    float x, y, z, vx, vy, vz;
+    __device__ void load(const KArena &A, int i)
+    {
+        float4 a = ((const float4 *)A.st[0])[i], b = ((const float4 *)A.st[1])[i];
+        x = a.x; y = a.y; z = a.z; vx = b.x; vy = b.y; vz = b.z;
+    }
+    __device__ void store(const KArena &A, int i) const
+    {
+        ((float4 *)A.st[0])[i] = make_float4(x, y, z, 0.0f);
+        ((float4 *)A.st[1])[i] = make_float4(vx, vy, vz, 0.0f);
+    }
+};
+
+template <> struct State<PREC_DS> {
+    dsf x, y, z, vx, vy, vz;
+    __device__ void load(const KArena &A, int i)
+    {
+        float4 a = ((const float4 *)A.st[0])[i], b = ((const float4 *)A.st[1])[i],
+               c = ((const float4 *)A.st[2])[i];
+        x = {a.x, a.w}; y = {a.y, b.x}; z = {a.z, b.y};
+        vx = {b.z, c.y}; vy = {b.w, c.z}; vz = {c.x, c.w};
+    }
+    __device__ void store(const KArena &A, int i) const
+    {
+        ((float4 *)A.st[0])[i] = make_float4(x.hi, y.hi, z.hi, x.lo);
+        ((float4 *)A.st[1])[i] = make_float4(y.lo, z.lo, vx.hi, vy.hi);
+        ((float4 *)A.st[2])[i] = make_float4(vz.hi, vx.lo, vy.lo, vz.lo);
+    }
+};
+
+struct StateD {
+    double x, y, z, vx, vy, vz;
+    __device__ void load(const KArena &A, int i)
+    {
+        double2 a = ((const double2 *)A.st[0])[i], b = ((const double2 *)A.st[1])[i],
+                c = ((const double2 *)A.st[2])[i];
+        x = a.x; y = a.y; z = b.x; vx = b.y; vy = c.x; vz = c.y;
+    }
+    __device__ void store(const KArena &A, int i) const
+    {
+        ((double2 *)A.st[0])[i] = make_double2(x, y);
+        ((double2 *)A.st[1])[i] = make_double2(z, vx);
+        ((double2 *)A.st[2])[i] = make_double2(vy, vz);
+    }
+};
+template <> struct State<PREC_MIX> : StateD {};
+template <> struct State<PREC_FP64> : StateD {};

@@ -1,5 +1,5 @@
-// Kernel argument blocks and launchers of libmdx (shared by kernels.hip and
-// the host engine).  Every argument block is passed by value.
+// Kernel argument blocks and launchers of libmdx (shared by the .hip kernel
+// sources and abi.cpp).  Plain structs passed by value as kernel arguments.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "md_dev.hpp"

@@ -1,0 +1,759 @@
+// Neighbour-list rebuild kernels (cell count, scan, stable sort, list build)
+// and their launchers.
+#include "dev_common.hpp"
+
+// ------------------------------------------------------------ k_count
+// Cell counts for a rebuild forced from the host (md_rebuild_neighbours).
+template <int P>
+__global__ void k_count(const CountArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.P) return;
+    constexpr int NS = Traits<P>::NS;
+    uint4 s0 = a.snap[i];
+    uint32_t meta;
+    double x = 0, y = 0, z = 0, w = 0;
+    if (NS == 2) {
+        u4_to_dbl2(s0, x, y);
+        u4_to_dbl2(a.snap[(size_t)a.P + i], z, w);
+        meta = meta_of_bits(w);
+    } else meta = s0.w;
+    if (meta == NO_SLOT) return;
+    int r = slot_of_meta(meta);
+    if (r >= a.max_slots) return;
+    if (!slot_selected(r, a.force_slot, nullptr, a.ctl)) return;
+    RepDev rp = a.rep[r];
+    int cell;
+    if (NS == 2) cell = dbl_cell(x, y, z, rp.L, rp.invL, rp.nd);
+    else cell = rp.nd == 1 ? 0 : fixed_cell(s0.x, s0.y, s0.z, rp.nd);
+    atomicAdd(a.count + rp.coff + cell, 1);
+}
+
+// ------------------------------------------------------------ k_scan
+// One workgroup (1024 threads) per slot: exclusive scan of the cell counts
+// in tiles of 8 cells per thread, cell starts written as absolute slots.
+__global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
+{
+    int s = blockIdx.x;
+    if (a.force_slot == -1) {
+        if (s >= a.rlist[0]) return;
+        s = a.rlist[1 + s];
+    } else {
+        if (s >= a.max_slots) return;
+        if (!slot_selected(s, a.force_slot, a.need, a.ctl)) return;
+    }
+    const RepDev rp = a.rep[s];
+    const int ncell = rp.nd * rp.nd * rp.nd;
+    const int B = blockDim.x, t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6, nw = (B + 63) >> 6;
+    const int *cnt = a.count + rp.coff;
+    int *out = a.cs_new + rp.coff;
+    __shared__ int wsum[16];
+    __shared__ int tile_total;
+    int carry = 0;
+    for (int base = 0; base < ncell; base += 8 * B) {
+        int v[8];
+        int local = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = base + 8 * t + u;
+            v[u] = c < ncell ? cnt[c] : 0;
+            local += v[u];
+        }
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int w = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += w;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        if (t == 0) {
+            int acc = 0;
+            for (int k = 0; k < nw; ++k) { const int w = wsum[k]; wsum[k] = acc; acc += w; }
+            tile_total = acc;
+        }
+        __syncthreads();
+        int run = rp.off + carry + wsum[wv] + incl - local;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = base + 8 * t + u;
+            if (c < ncell) out[c] = run;
+            run += v[u];
+        }
+        carry += tile_total;
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[ncell] = rp.off + carry;
+        if (carry != rp.n) atomicOr(a.status + s, 4 | 2);
+        a.nreb[s] += 1;
+    }
+}
+
+// ------------------------------------------------------------ k_permute
+// One wave per new cell: stable scatter of its members into scratch.  Each
+// pass first loads every member it moves, then folds and stores them: on
+// this hardware one counter tracks loads and stores alike, so a load issued
+// after a store would also wait for that store.
+template <int P> struct Moved {
+    uint4 st[Traits<P>::NW];
+    int4 meta;
+    uint4 snap; // the snapshot (fixed point), or its second word (double)
+};
+
+template <int P>
+__device__ __forceinline__ void move_load(const PermArgs &a, int q, Moved<P> &mv)
+{
+    constexpr int NW = Traits<P>::NW, NS = Traits<P>::NS;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) mv.st[w] = a.A.st[w][q];
+    mv.meta = a.A.meta[q];
+    mv.snap = NS == 1 ? a.snap[q] : a.snap[(size_t)a.A.P + q];
+}
+
+__device__ __forceinline__ float4 u4_as_f4(uint4 u)
+{
+    return make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
+}
+__device__ __forceinline__ uint4 f4_as_u4(float4 f)
+{
+    return make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w));
+}
+
+// Fold the member's position into [0, L) (counting the image shift in its
+// meta word) and store it at scratch slot dst.
+template <int P>
+__device__ __forceinline__ void move_store(const PermArgs &a, const RepDev &rp, const Moved<P> &mv, int dst)
+{
+    constexpr int NS = Traits<P>::NS;
+    int4 m = mv.meta;
+    int ix = 0, iy = 0, iz = 0;
+    int *im[3] = {&ix, &iy, &iz};
+    if constexpr (P == PREC_FP32) {
+        float4 p = u4_as_f4(mv.st[0]);
+        float *c[3] = {&p.x, &p.y, &p.z};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (*c[d] < 0.0f) { *c[d] += rp.Lf; *im[d] -= 1; }
+            if (*c[d] >= rp.Lf) { *c[d] -= rp.Lf; *im[d] += 1; }
+        }
+        a.sc_st[0][dst] = f4_as_u4(p);
+        a.sc_st[1][dst] = mv.st[1];
+    } else if constexpr (P == PREC_DS) {
+        const float4 w0 = u4_as_f4(mv.st[0]), w1 = u4_as_f4(mv.st[1]);
+        dsf x = {w0.x, w0.w}, y = {w0.y, w1.x}, z = {w0.z, w1.y};
+        const dsf L = {rp.L_hi, rp.L_lo};
+        dsf *c[3] = {&x, &y, &z};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (c[d]->hi < 0.0f) { *c[d] = ds_add(*c[d], L); *im[d] -= 1; }
+            const dsf t = ds_sub(*c[d], L);
+            if (t.hi >= 0.0f) { *c[d] = t; *im[d] += 1; }
+        }
+        a.sc_st[0][dst] = f4_as_u4(make_float4(x.hi, y.hi, z.hi, x.lo));
+        a.sc_st[1][dst] = f4_as_u4(make_float4(y.lo, z.lo, w1.z, w1.w));
+        a.sc_st[2][dst] = mv.st[2];
+    } else {
+        double x, y, z, w;
+        u4_to_dbl2(mv.st[0], x, y);
+        u4_to_dbl2(mv.st[1], z, w);
+        double *c[3] = {&x, &y, &z};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (*c[d] < 0.0) { *c[d] += rp.L; *im[d] -= 1; }
+            if (*c[d] >= rp.L) { *c[d] -= rp.L; *im[d] += 1; }
+        }
+        a.sc_st[0][dst] = dbl2_to_u4(x, y);
+        a.sc_st[1][dst] = dbl2_to_u4(z, w);
+        a.sc_st[2][dst] = mv.st[2];
+        if constexpr (NS == 2) { // the double snapshot, from the folded state
+            double zz, ww;
+            u4_to_dbl2(mv.snap, zz, ww);
+            a.sc_snap[dst] = dbl2_to_u4(x, y);
+            a.sc_snap[(size_t)a.A.P + dst] = dbl2_to_u4(z, ww);
+        }
+    }
+    m.x += ix; m.y += iy; m.z += iz;
+    a.sc_meta[dst] = m;
+    if constexpr (NS == 1) a.sc_snap[dst] = mv.snap;
+}
+
+template <int P>
+__device__ __forceinline__ bool in_cell(const PermArgs &a, const RepDev &rp, int q, int c)
+{
+    constexpr int NS = Traits<P>::NS;
+    if (NS == 2) {
+        double x, y, z, w;
+        u4_to_dbl2(a.snap[q], x, y);
+        u4_to_dbl2(a.snap[(size_t)a.A.P + q], z, w);
+        return dbl_cell(x, y, z, rp.L, rp.invL, rp.nd) == c;
+    }
+    const uint4 X = a.snap[q];
+    return fixed_cell(X.x, X.y, X.z, rp.nd) == c;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_permute(const PermArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int wv = threadIdx.x >> 6;
+    __shared__ int pref[4][28], pst[4][27];
+    for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 3,
+              blockIdx.x * wpb + wv, gridDim.x * wpb, [&](int s, int c) {
+        const RepDev rp = a.rep[s];
+        const int nd = rp.nd;
+        const int *cs = a.cs + rp.coff;
+        const int dst0 = a.cs_new[rp.coff + c];
+        const int want = a.cs_new[rp.coff + c + 1] - dst0;
+        // the old cells that can hold members of new cell c, ascending (so
+        // that the flattened candidates are in old slot order)
+        int nold = 1;
+        if (lane == 0) { pst[wv][0] = cs[0]; pref[wv][0] = 0; pref[wv][1] = cs[1] - cs[0]; }
+        if (nd > 1) {
+            nold = 27;
+            const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
+            int v[3][3] = {{(cx + nd - 1) % nd, cx, (cx + 1) % nd},
+                           {(cy + nd - 1) % nd, cy, (cy + 1) % nd},
+                           {(cz + nd - 1) % nd, cz, (cz + 1) % nd}};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int *u = v[d];
+                if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+                if (u[1] > u[2]) { int t = u[1]; u[1] = u[2]; u[2] = t; }
+                if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+            }
+            int len = 0, st0 = 0;
+            if (lane < 27) {
+                const int kx = lane % 3, ky = (lane / 3) % 3, kz = lane / 9;
+                const int oc = v[0][kx] + nd * (v[1][ky] + nd * v[2][kz]);
+                st0 = cs[oc];
+                len = cs[oc + 1] - st0;
+            }
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
+            }
+            if (lane < 27) { pst[wv][lane] = st0; pref[wv][lane + 1] = incl; }
+            if (lane == 0) pref[wv][0] = 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int tot = pref[wv][nold];
+        int run = 0;
+        int r = 0; // old cell of the lane's current candidate (only moves forward)
+        constexpr int U = 4; // candidates per lane per pass
+        for (int b = 0; b < tot; b += 64 * U) {
+            int q[U];
+            bool m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = b + 64 * u + lane;
+                q[u] = -1;
+                if (e < tot) {
+                    while (r + 1 < nold && pref[wv][r + 1] <= e) ++r;
+                    q[u] = pst[wv][r] + (e - pref[wv][r]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) m[u] = q[u] >= 0 && (nd == 1 || in_cell<P>(a, rp, q[u], c));
+            Moved<P> mv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (m[u]) move_load<P>(a, q[u], mv[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned long long bal = __ballot(m[u]);
+                if (m[u]) move_store<P>(a, rp, mv[u], dst0 + run + __popcll(bal & ((1ull << lane) - 1ull)));
+                run += __popcll(bal);
+            }
+        }
+        // every particle counted in this cell must have come from a
+        // neighbouring old cell; a shortfall means a particle jumped further
+        if (lane == 0 && run != want) atomicOr(a.status + s, 4);
+        __builtin_amdgcn_wave_barrier();
+    });
+}
+
+// ------------------------------------------------------------ k_build
+// One workgroup per row segment of cells (cells x0..x1-1 of row (y, z)):
+// the 9 neighbouring rows over x0-1..x1 are staged in LDS, then every member
+// writes its list in the canonical order.
+#define BUILD_LDS_CAP 3072 // staged candidates (x 16 B = 48 KB, fixed point)
+#define BUILD_MAX_NX 18    // cells per staged row (width + 2 halo)
+#define BUILD_TAB (9 * BUILD_MAX_NX)
+
+struct BuildTabs {
+    int start[BUILD_TAB]; // LDS start of staged cell (global start when not staged)
+    int cnt[BUILD_TAB];
+    int glob[BUILD_TAB];  // global start of the cell
+    int4 pk[BUILD_TAB];   // (start, cnt, glob) of each staged cell, for the grouped scan
+    int run_lds[19], run_glob[19];
+    int nruns, total, fits, NX;
+};
+
+template <int P, bool FROM_LDS>
+__device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
+                                             const BuildTabs &T, bool full, const uint4 *cand, int s,
+                                             int nd)
+{
+    constexpr int NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    const size_t P_ = (size_t)A.P;
+    const int NX = T.NX;
+    uint4 xi = a.src_x[i];
+    double xd = 0, yd = 0, zd = 0, wd = 0;
+    uint32_t meta;
+    if (NS == 2) {
+        u4_to_dbl2(xi, xd, yd);
+        u4_to_dbl2(a.src_x[P_ + i], zd, wd);
+        meta = meta_of_bits(wd);
+    } else meta = xi.w;
+    const int si = (int)(meta & SPECIES_MASK);
+    float rl2s0, rl2s1;
+    double rl2d0 = a.pp.rl2d[si * 2], rl2d1 = a.pp.rl2d[si * 2 + 1];
+    {
+        const double u = (double)rp.sc;
+        rl2s0 = (float)(rl2d0 / (u * u));
+        rl2s1 = (float)(rl2d1 / (u * u));
+    }
+    const int cap = A.cap;
+    // entry k of slot i: int4 row k/4, lane k%4 (see list_row)
+    int *col = A.nbr_w + 4 * (size_t)i;
+    const size_t row_stride = 4 * P_;
+    int cnt = 0;
+    int *wp = col; // where entry cnt goes
+    auto test = [&](int e, int st) -> bool {
+        if (NS == 2) {
+            double xj, yj, zj, wj;
+            if (FROM_LDS) {
+                u4_to_dbl2(cand[2 * (st + e)], xj, yj);
+                u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
+            } else {
+                u4_to_dbl2(a.src_x[st + e], xj, yj);
+                u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
+            }
+            double dx = xd - xj, dy = yd - yj, dz = zd - zj;
+            dx -= rp.L * rint(dx * rp.invL);
+            dy -= rp.L * rint(dy * rp.invL);
+            dz -= rp.L * rint(dz * rp.invL);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
+        }
+        const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+        const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
+                    dz = (float)(int)(xi.z - xj.z);
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
+    };
+    // Candidates of one cell in slot order; accepted ones are stored at once
+    // (a predicated 4-byte store).  `self` is the candidate index of i in
+    // this cell, or -1.
+    auto put = [&](bool acc, int j) {
+        if (acc) {
+            if (cnt < cap) *wp = j;
+            ++cnt;
+            wp += (cnt & 3) ? 1 : (ptrdiff_t)row_stride - 3;
+        }
+    };
+    // four candidates per iteration: independent reads and tests in flight
+    // (the scan is a dependent chain per member), stores in slot order
+    auto scan_cell = [&](int k, int self) {
+        const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+        int e = 0;
+        for (; e + 4 <= n; e += 4) {
+            const bool c0 = test(e, st), c1 = test(e + 1, st), c2 = test(e + 2, st), c3 = test(e + 3, st);
+            put(c0 && e != self, g0 + e);
+            put(c1 && e + 1 != self, g0 + e + 1);
+            put(c2 && e + 2 != self, g0 + e + 2);
+            put(c3 && e + 3 != self, g0 + e + 3);
+        }
+        for (; e < n; ++e) put(test(e, st) && e != self, g0 + e);
+    };
+    int last_cell = 0;
+    if (nd == 1) {
+        scan_cell(0, i - T.glob[0]);
+    } else {
+        // own cell, then each half-space offset o followed by -o: in the
+        // (dz, dy, dx) enumeration of the 27 offsets the positive half space
+        // is indices 14..26
+        auto cell_k = [&](int dx, int dy, int dz) {
+            int lx = lx_m + dx;
+            if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
+            return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
+        };
+        const int own = cell_k(0, 0, 0);
+        scan_cell(own, i - T.glob[own]);
+        for (int q = 14; q < 27; ++q) {
+            const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
+            scan_cell(cell_k(dx, dy, dz), -1);
+            last_cell = cell_k(-dx, -dy, -dz);
+            scan_cell(last_cell, -1);
+        }
+    }
+    // Pad the list to a multiple of 8 with a particle that is outside the
+    // list radius at this build: it stays beyond the force cutoff until the
+    // next build (each particle moves at most skin/2), so the force loop
+    // needs no per-entry validity test.  The pad is the first rejected
+    // candidate of the last cell visited (a corner cell), else of any cell.
+    if (cnt & 7) {
+        int pad = -1;
+        {
+            const int st = T.start[last_cell], n = T.cnt[last_cell], g0 = T.glob[last_cell];
+            for (int e = 0; e < n && pad < 0; ++e)
+                if (!test(e, st) && g0 + e != i) pad = g0 + e;
+        }
+        for (int k = 0; k < (nd == 1 ? 1 : 9 * NX) && pad < 0; ++k) {
+            const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+            for (int e = 0; e < n && pad < 0; ++e)
+                if (!test(e, st) && g0 + e != i) pad = g0 + e;
+        }
+        if (pad < 0) atomicOr(a.status + s, 8);
+        for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
+            col[(size_t)(k >> 2) * row_stride + (k & 3)] = pad < 0 ? i : pad;
+    }
+    A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
+    if (cnt > A.cap) atomicOr(a.status + s, 1);
+}
+
+// The same list, built by a group of G lanes (G a power of two <= 64, the
+// group's lanes adjacent in one wave): the member's candidates, concatenated
+// in the canonical cell order, are tested G at a time, one per lane, and the
+// accepted ones are stored at the running count plus their rank among the
+// group's accepted lanes (ballot + popcount), i.e. in exactly the order of
+// the one-lane scan.  Splits one member's dependent candidate chain G ways,
+// which is what bounds the build of small replicas.
+template <int P, bool FROM_LDS>
+__device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
+                                                 const BuildTabs &T, bool full, const uint4 *cand, int s,
+                                                 int nd, int G, int gl, unsigned long long gmask,
+                                                 unsigned long long below)
+{
+    constexpr int NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    const size_t P_ = (size_t)A.P;
+    const int NX = T.NX;
+    uint4 xi = a.src_x[i];
+    double xd = 0, yd = 0, zd = 0, wd = 0;
+    uint32_t meta;
+    if (NS == 2) {
+        u4_to_dbl2(xi, xd, yd);
+        u4_to_dbl2(a.src_x[P_ + i], zd, wd);
+        meta = meta_of_bits(wd);
+    } else meta = xi.w;
+    const int si = (int)(meta & SPECIES_MASK);
+    float rl2s0, rl2s1;
+    double rl2d0 = a.pp.rl2d[si * 2], rl2d1 = a.pp.rl2d[si * 2 + 1];
+    {
+        const double u = (double)rp.sc;
+        rl2s0 = (float)(rl2d0 / (u * u));
+        rl2s1 = (float)(rl2d1 / (u * u));
+    }
+    const int cap = A.cap;
+    int *col = A.nbr_w + 4 * (size_t)i;
+    const size_t row_stride = 4 * P_;
+    auto test = [&](int e, int st) -> bool {
+        if (NS == 2) {
+            double xj, yj, zj, wj;
+            if (FROM_LDS) {
+                u4_to_dbl2(cand[2 * (st + e)], xj, yj);
+                u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
+            } else {
+                u4_to_dbl2(a.src_x[st + e], xj, yj);
+                u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
+            }
+            double dx = xd - xj, dy = yd - yj, dz = zd - zj;
+            dx -= rp.L * rint(dx * rp.invL);
+            dy -= rp.L * rint(dy * rp.invL);
+            dz -= rp.L * rint(dz * rp.invL);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
+        }
+        const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+        const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
+                    dz = (float)(int)(xi.z - xj.z);
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
+    };
+    // one cell's candidates, 4G at a time: lane gl tests e = b + u G + gl
+    // (u = 0..3, independent loads in flight); the ballots are taken in u
+    // order, which is ascending e
+    int cnt = 0;
+    auto scan_cell = [&](int k) {
+        const int4 c = T.pk[k]; // (start, cnt, glob)
+        for (int b = 0; b < c.y; b += 4 * G) {
+            bool acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = b + u * G + gl;
+                acc[u] = e < c.y && test(e, c.x) && c.z + e != i;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned long long m = __ballot(acc[u]) & gmask;
+                if (acc[u]) {
+                    const int k2 = cnt + __popcll(m & below);
+                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = c.z + b + u * G + gl;
+                }
+                cnt += __popcll(m);
+            }
+        }
+    };
+    // visiting order: own cell, then +o, -o for q = 14..26 of the
+    // (dz, dy, dx) enumeration of the 27 offsets
+    auto cell_k = [&](int dx, int dy, int dz) {
+        int lx = lx_m + dx;
+        if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
+        return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
+    };
+    int last_cell = 0;
+    if (nd == 1) {
+        scan_cell(0);
+    } else {
+        scan_cell(cell_k(0, 0, 0));
+        for (int q = 14; q < 27; ++q) {
+            const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
+            scan_cell(cell_k(dx, dy, dz));
+            last_cell = cell_k(-dx, -dy, -dz);
+            scan_cell(last_cell);
+        }
+    }
+    // pad to a multiple of 8, as in the one-lane build: the first rejected
+    // candidate of the last visited cell, else (rare) of any staged cell
+    if (cnt & 7) {
+        int pad = -1;
+        const int4 cl = T.pk[last_cell];
+        for (int b = 0; b < cl.y; b += G) {
+            const int e = b + gl;
+            const bool r = e < cl.y && !test(e, cl.x) && cl.z + e != i;
+            const unsigned long long m = __ballot(r) & gmask;
+            if (m) { pad = cl.z + b + (__ffsll(m) - 1) - (__ffsll(gmask) - 1); break; }
+        }
+        if (gl == 0) {
+            for (int k = 0; k < (nd == 1 ? 1 : 9 * NX) && pad < 0; ++k) {
+                const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+                for (int e = 0; e < n && pad < 0; ++e)
+                    if (!test(e, st) && g0 + e != i) pad = g0 + e;
+            }
+            if (pad < 0) atomicOr(a.status + s, 8);
+            for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
+                col[(size_t)(k >> 2) * row_stride + (k & 3)] = pad < 0 ? i : pad;
+        }
+    }
+    if (gl == 0) {
+        A.nbr_cnt_w[i] = cnt < cap ? cnt : cap;
+        if (cnt > cap) atomicOr(a.status + s, 1);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void copy_back(const BuildArgs &a, int i)
+{
+    constexpr int NW = Traits<P>::NW, NS = Traits<P>::NS;
+    const KArena &A = a.A;
+    const size_t P_ = (size_t)A.P;
+    if (a.from_scratch) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) A.st[w][i] = a.sc_st[w][i];
+        A.meta[i] = a.sc_meta[i];
+#pragma unroll
+        for (int w = 0; w < NS; ++w) {
+            uint4 x = a.src_x[w * P_ + i];
+            a.snap_cur[w * P_ + i] = x;
+            A.xref_w[w * P_ + i] = x;
+        }
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
+{
+    constexpr int NS = Traits<P>::NS;
+    __shared__ BuildTabs T;
+    extern __shared__ uint4 cand[];
+    const int B = blockDim.x, t = threadIdx.x;
+    for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 4,
+              remap_block(blockIdx.x, gridDim.x, a.xcd), gridDim.x, [&](int s, int item) {
+        const RepDev rp = a.rep[s];
+        const int nd = rp.nd;
+        const int *cs = a.cs_new + rp.coff;
+        int m0, m1, NX = 1, x0 = 0, x1 = 1, rowbase = 0;
+        bool full = true;
+        if (nd == 1) {
+            m0 = rp.off + item * a.single_members;
+            m1 = min(m0 + a.single_members, rp.off + rp.n);
+            if (t == 0) {
+                T.glob[0] = rp.off;
+                T.cnt[0] = rp.n;
+                T.start[0] = 0;
+                T.run_lds[0] = 0; T.run_glob[0] = rp.off; T.run_lds[1] = rp.n;
+                T.nruns = 1;
+                T.total = rp.n;
+                T.fits = rp.n <= a.lds_cap;
+                if (!T.fits) T.start[0] = rp.off;
+                T.NX = 1;
+                if (item == 0 && a.from_scratch) { a.cs[rp.coff] = cs[0]; a.cs[rp.coff + 1] = cs[1]; }
+            }
+        } else {
+            const int W = a.width;
+            full = nd <= W + 2;
+            const int nseg = full ? 1 : (nd + W - 1) / W;
+            const int part = item % rp.bparts, segitem = item / rp.bparts;
+            const int seg = segitem % nseg, row = segitem / nseg;
+            const int cy = row % nd, cz = row / nd;
+            x0 = full ? 0 : (seg * nd) / nseg;           // balanced segments
+            x1 = full ? nd : ((seg + 1) * nd) / nseg;
+            NX = full ? nd : x1 - x0 + 2;
+            rowbase = nd * (cy + nd * cz);
+            {   // this item's share of the segment's members
+                const int s0 = cs[rowbase + x0], ms = cs[rowbase + x1] - s0;
+                m0 = s0 + (int)(((long long)part * ms) / rp.bparts);
+                m1 = s0 + (int)(((long long)(part + 1) * ms) / rp.bparts);
+            }
+            if (a.from_scratch && part == 0) { // retire the old cell starts of this segment
+                for (int k = x0 + t; k < x1; k += B) a.cs[rp.coff + rowbase + k] = cs[rowbase + k];
+                if (t == 0 && rowbase + x1 == nd * nd * nd)
+                    a.cs[rp.coff + nd * nd * nd] = cs[nd * nd * nd];
+            }
+            const int gs = full ? 0 : (x0 - 1 + nd) % nd; // first staged x
+            for (int k = t; k < 9 * NX; k += B) {
+                const int rw = k / NX, lx = k - rw * NX;
+                const int dz = rw / 3 - 1, dy = rw % 3 - 1;
+                int gx = gs + lx;
+                gx -= gx >= nd ? nd : 0;
+                int gy = cy + dy, gz = cz + dz;
+                gy += gy < 0 ? nd : 0; gy -= gy >= nd ? nd : 0;
+                gz += gz < 0 ? nd : 0; gz -= gz >= nd ? nd : 0;
+                const int cc = gx + nd * (gy + nd * gz);
+                T.glob[k] = cs[cc];
+                T.cnt[k] = cs[cc + 1] - cs[cc];
+            }
+            if (t == 0) T.NX = NX;
+            __syncthreads();
+            if (t < 64) { // exclusive scan of the staged cell sizes (one wave)
+                const int ncells = 9 * NX;
+                int carry = 0;
+                for (int b = 0; b < ncells; b += 64) {
+                    const int k = b + t;
+                    const int v = k < ncells ? T.cnt[k] : 0;
+                    int incl = v;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int u = __shfl_up(incl, o, 64);
+                        if (t >= o) incl += u;
+                    }
+                    if (k < ncells) T.start[k] = carry + incl - v;
+                    carry += __shfl(incl, 63, 64);
+                }
+                if (t == 0) { T.total = carry; T.fits = carry <= a.lds_cap; }
+            }
+            __syncthreads();
+            if (t < 9) { // contiguous global runs of each staged row (<= 2 with wrap)
+                const int lenA = full ? NX : min(NX, nd - gs);
+                const int k0 = t * NX;
+                T.run_lds[2 * t] = T.start[k0];
+                T.run_glob[2 * t] = T.glob[k0];
+                T.run_lds[2 * t + 1] = lenA < NX ? T.start[k0 + lenA] : T.start[k0 + NX - 1] + T.cnt[k0 + NX - 1];
+                T.run_glob[2 * t + 1] = lenA < NX ? T.glob[k0 + lenA] : T.glob[k0 + NX - 1] + T.cnt[k0 + NX - 1];
+                if (t == 8) { T.run_lds[18] = T.total; T.nruns = 18; }
+            }
+            __syncthreads();
+            if (!T.fits) // candidates are read from the arena: start = global index
+                for (int k = t; k < 9 * NX; k += B) T.start[k] = T.glob[k];
+        }
+        __syncthreads();
+        for (int k = t; k < (nd == 1 ? 1 : 9 * NX); k += B) T.pk[k] = make_int4(T.start[k], T.cnt[k], T.glob[k], 0);
+        const bool fits = T.fits != 0;
+        if (fits) { // stage: element e lies in the last run whose LDS start is <= e
+            const int tot = T.total, nr = T.nruns;
+            int r = 0; // only moves forward as e grows
+            for (int e = t; e < tot; e += B) {
+                while (r + 1 < nr && T.run_lds[r + 1] <= e) ++r;
+                const int g = T.run_glob[r] + (e - T.run_lds[r]);
+                if (NS == 2) {
+                    cand[2 * e] = a.src_x[g];
+                    cand[2 * e + 1] = a.src_x[(size_t)a.A.P + g];
+                } else cand[e] = a.src_x[g];
+            }
+        }
+        __syncthreads();
+        // the member's cell: own-row staged cell whose range holds i
+        auto member_cell = [&](int i) {
+            if (nd == 1) return 0;
+            int lx = full ? 0 : 1;
+            const int le = full ? NX - 1 : NX - 2;
+            while (lx < le && T.glob[4 * NX + lx + 1] <= i) ++lx;
+            return lx;
+        };
+        // lanes per member: the replica's (fixed by the launch, or one lane
+        // for large replicas), else the largest power of two that still
+        // gives every member of this work item its own group
+        int G = rp.blanes;
+        if (G == 0) {
+            G = 1;
+            while (G < 64 && (2 * G) * (m1 - m0) <= B) G *= 2;
+        }
+        if (G == 1) {
+            for (int i = m0 + t; i < m1; i += B) {
+                const int lx_m = member_cell(i);
+                if (fits) build_member<P, true>(a, rp, i, lx_m, T, full, cand, s, nd);
+                else build_member<P, false>(a, rp, i, lx_m, T, full, cand, s, nd);
+                copy_back<P>(a, i);
+            }
+        } else {
+            const int lane = t & 63, gl = t & (G - 1);
+            const unsigned long long gmask =
+                G == 64 ? ~0ull : ((1ull << G) - 1ull) << (lane & ~(G - 1));
+            const unsigned long long below = (1ull << lane) - 1ull;
+            for (int i = m0 + t / G; i < m1; i += B / G) {
+                const int lx_m = member_cell(i);
+                if (fits) build_member_grp<P, true>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
+                else build_member_grp<P, false>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
+                if (gl == 0) copy_back<P>(a, i);
+            }
+        }
+        __syncthreads();
+    });
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s)
+{
+    int grid = (a.P + 255) / 256;
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL((k_count<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_count<PREC_FP32>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan, dim3(a.max_slots), dim3(1024), 0, s, a);
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_permute(int prec, const PermArgs &a, int grid, hipStream_t s)
+{
+    switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((k_permute<PREC_FP32>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_DS: hipLaunchKernelGGL((k_permute<PREC_DS>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_MIX: hipLaunchKernelGGL((k_permute<PREC_MIX>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_permute<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipStream_t s)
+{
+    size_t lds = (size_t)a.lds_cap * 16 * (prec == PREC_FP64 ? 2 : 1);
+    switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((k_build<PREC_FP32>), dim3(grid), dim3(block), lds, s, a); break;
+    case PREC_DS: hipLaunchKernelGGL((k_build<PREC_DS>), dim3(grid), dim3(block), lds, s, a); break;
+    case PREC_MIX: hipLaunchKernelGGL((k_build<PREC_MIX>), dim3(grid), dim3(block), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_build<PREC_FP64>), dim3(grid), dim3(block), lds, s, a); break;
+    }
+    LAUNCH_CHECK();
+}

@@ -1,0 +1,488 @@
+// The fused force + velocity-Verlet step kernel (k_step) and its launcher.
+#include "dev_common.hpp"
+
+// ---------------------------------------------------- force accumulators
+template <int P> struct FAcc;
+
+template <> struct FAcc<PREC_FP32> {
+    float x, y, z;
+    __device__ void init() { x = y = z = 0.0f; }
+    __device__ void add(float fs, float dx, float dy, float dz, int, int, int)
+    {
+        x = __builtin_fmaf(fs, dx, x);
+        y = __builtin_fmaf(fs, dy, y);
+        z = __builtin_fmaf(fs, dz, z);
+    }
+    __device__ void get(double &fx, double &fy, double &fz) const { fx = x; fy = y; fz = z; }
+};
+
+template <> struct FAcc<PREC_DS> {
+    sum2f x, y, z;
+    __device__ void init() { x.init(); y.init(); z.init(); }
+    __device__ void add(float fs, float dx, float dy, float dz, int, int, int)
+    {
+        x.add(fs * dx);
+        y.add(fs * dy);
+        z.add(fs * dz);
+    }
+    __device__ void get(double &fx, double &fy, double &fz) const
+    {
+        fx = ds_to_double(x.result()); fy = ds_to_double(y.result()); fz = ds_to_double(z.result());
+    }
+};
+
+template <> struct FAcc<PREC_MIX> {
+    double x, y, z;
+    __device__ void init() { x = y = z = 0.0; }
+    __device__ void add(float fs, float, float, float, int ix, int iy, int iz)
+    {
+        double f = (double)fs;
+        x = __builtin_fma(f, (double)ix, x);
+        y = __builtin_fma(f, (double)iy, y);
+        z = __builtin_fma(f, (double)iz, z);
+    }
+    __device__ void get(double &fx, double &fy, double &fz) const { fx = x; fy = y; fz = z; }
+};
+
+// Butterfly sum of the partial sums of the LPP lanes that share a particle
+// (lanes 2^k apart exchange; every step is a commutative add, so all lanes
+// of the group end with the same bits).
+__device__ __forceinline__ void lane_sum(float &x, int m) { x += __shfl_xor(x, m, 64); }
+__device__ __forceinline__ void lane_sum(double &x, int m) { x += __shfl_xor(x, m, 64); }
+__device__ __forceinline__ void lane_sum(dsf &x, int m)
+{
+    dsf o = {__shfl_xor(x.hi, m, 64), __shfl_xor(x.lo, m, 64)};
+    x = ds_add(x, o);
+}
+
+// ------------------------------------------------------------ integration
+// Velocity-Verlet pieces: kick v += (dt/2m) F, drift r += dt v.
+__device__ __forceinline__ void kick(State<PREC_FP32> &s, const FAcc<PREC_FP32> &f, const IntegDev &g)
+{
+    s.vx = __builtin_fmaf(g.hf, f.x, s.vx);
+    s.vy = __builtin_fmaf(g.hf, f.y, s.vy);
+    s.vz = __builtin_fmaf(g.hf, f.z, s.vz);
+}
+__device__ __forceinline__ void drift(State<PREC_FP32> &s, const IntegDev &g)
+{
+    s.x = __builtin_fmaf(g.dtf, s.vx, s.x);
+    s.y = __builtin_fmaf(g.dtf, s.vy, s.y);
+    s.z = __builtin_fmaf(g.dtf, s.vz, s.z);
+}
+
+struct DsForce { dsf x, y, z; };
+__device__ __forceinline__ void kick(State<PREC_DS> &s, const DsForce &f, const IntegDev &g)
+{
+    dsf h = {g.h_hi, g.h_lo};
+    s.vx = ds_add(s.vx, ds_mul(f.x, h));
+    s.vy = ds_add(s.vy, ds_mul(f.y, h));
+    s.vz = ds_add(s.vz, ds_mul(f.z, h));
+}
+__device__ __forceinline__ void drift(State<PREC_DS> &s, const IntegDev &g)
+{
+    dsf dt = {g.dt_hi, g.dt_lo};
+    s.x = ds_add(s.x, ds_mul(s.vx, dt));
+    s.y = ds_add(s.y, ds_mul(s.vy, dt));
+    s.z = ds_add(s.z, ds_mul(s.vz, dt));
+}
+
+__device__ __forceinline__ void kickd(StateD &s, double fx, double fy, double fz, const IntegDev &g)
+{
+    s.vx = __builtin_fma(g.h, fx, s.vx);
+    s.vy = __builtin_fma(g.h, fy, s.vy);
+    s.vz = __builtin_fma(g.h, fz, s.vz);
+}
+__device__ __forceinline__ void driftd(StateD &s, const IntegDev &g)
+{
+    s.x = __builtin_fma(g.dt, s.vx, s.x);
+    s.y = __builtin_fma(g.dt, s.vy, s.y);
+    s.z = __builtin_fma(g.dt, s.vz, s.z);
+}
+
+// Fixed-point snapshot of a state's position.
+__device__ __forceinline__ uint4 snap_of(const State<PREC_FP32> &s, const RepDev &r, uint32_t w)
+{
+    return make_uint4(to_fixed((double)s.x, r.fxs), to_fixed((double)s.y, r.fxs), to_fixed((double)s.z, r.fxs), w);
+}
+__device__ __forceinline__ uint4 snap_of(const State<PREC_DS> &s, const RepDev &r, uint32_t w)
+{
+    return make_uint4(to_fixed(ds_to_double(s.x), r.fxs), to_fixed(ds_to_double(s.y), r.fxs),
+                      to_fixed(ds_to_double(s.z), r.fxs), w);
+}
+__device__ __forceinline__ uint4 snap_of(const StateD &s, const RepDev &r, uint32_t w)
+{
+    return make_uint4(to_fixed(s.x, r.fxs), to_fixed(s.y, r.fxs), to_fixed(s.z, r.fxs), w);
+}
+
+// ------------------------------------------------ pair constants per lane
+// Scaled units: separations in fixed-point units u = L / 2^32.  With
+// r2s = r^2 / u^2 the pair term needs rc^2/u^2, sigma^2/u^2 and 24 eps / u.
+struct LaneConsts {
+    float rc2s[2], sig2s[2], e24s[2];
+};
+
+__device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, const RepDev &r)
+{
+    LaneConsts c;
+    double u = (double)r.sc;
+    double iu2 = 1.0 / (u * u);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        int t = si * 2 + b;
+        c.rc2s[b] = (float)(pp.rc2d[t] * iu2);
+        c.sig2s[b] = (float)(pp.sig2d[t] * iu2);
+        c.e24s[b] = (float)(pp.eps24d[t] / u);
+    }
+    return c;
+}
+
+// The Verlet list of particle i is stored in blocks of four entries:
+// entry k lives in int4 row k/4, lane k%4, of column i (nbr4[(k/4)*P + i]),
+// so one dwordx4 load fetches four indices and a wave reads 1 KB contiguous.
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 list_row(const KArena &A, int i, int q)
+{
+    const v4i *p = (const v4i *)A.nbr + (size_t)q * A.P + i;
+    v4i v = __builtin_nontemporal_load(p); // streamed once per step: keep it out of the caches
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
+// One list entry, fixed-point snapshots, FP32 pair term.  With a uniform
+// cutoff ratio (rc_ab = c sigma_ab for every pair) the cutoff test is
+// sigma^2/r^2 > 1/c^2 and needs no per-pair cutoff.
+template <int P, bool EN, bool UNI>
+__device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts &c, const PairDev &pp,
+                                            int si, FAcc<P> &acc, double &e_sum, double &w_sum)
+{
+    const int ix = (int)(xi.x - xj.x), iy = (int)(xi.y - xj.y), iz = (int)(xi.z - xj.z);
+    const float dx = (float)ix, dy = (float)iy, dz = (float)iz;
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const bool b = (xj.w & SPECIES_MASK) != 0;
+    const float sig2 = b ? c.sig2s[1] : c.sig2s[0];
+    const float e24 = b ? c.e24s[1] : c.e24s[0];
+    const float ir2 = __builtin_amdgcn_rcpf(r2);
+    const float s2 = sig2 * ir2;
+    const float s6 = s2 * s2 * s2;
+    const float t = __builtin_fmaf(2.0f, s6, -1.0f);
+    float fs = e24 * ir2 * s6 * t;
+    bool in;
+    if (UNI) in = s2 > pp.s2cut;
+    else in = r2 < (b ? c.rc2s[1] : c.rc2s[0]);
+    fs = in ? fs : 0.0f;
+    acc.add(fs, dx, dy, dz, ix, iy, iz);
+    if (EN) {
+        const int tt = si * 2 + (b ? 1 : 0);
+        if (in) {
+            e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
+            w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
+        }
+    }
+}
+
+// Snapshot gather with a 32-bit byte offset from a uniform base.
+__device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int j)
+{
+    return *(const uint4 *)((const char *)snap + (uint32_t)j * 16u);
+}
+
+// Force (and optionally energy/virial) on particle i from its list.  The
+// loop is software-pipelined over blocks of four entries with two register
+// buffers: while one block is computed, the snapshots of the next block and
+// the indices of the block after it are in flight.  Lists are padded to a
+// multiple of eight valid entries by the list build and row indices are clamped, so every
+// prefetch is unconditional and no control-flow join forces the memory
+// counters to drain inside the loop.
+template <int P, bool EN, bool UNI>
+__device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
+                                            uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
+                                            FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp)
+{
+    const int cnt = A.nbr_cnt[i];
+    const int nq = ((cnt + 7) >> 3) << 1; // blocks of four, padded to an even count
+    acc.init();
+    const int npair = nq >> 1;            // this lane takes pairs sub, sub + lpp, ...
+    if (sub >= npair) return;
+    const int last = nq - 1;
+    int p = sub;
+    // indices two blocks ahead, snapshots one block ahead
+    int4 ja = list_row(A, i, 2 * p), jb = list_row(A, i, 2 * p + 1);
+    uint4 a0 = ld_snap(snap, ja.x), a1 = ld_snap(snap, ja.y), a2 = ld_snap(snap, ja.z),
+          a3 = ld_snap(snap, ja.w);
+    ja = list_row(A, i, min(2 * (p + lpp), last));
+    for (; p < npair; p += lpp) {
+        // (the scheduling barriers keep each batch of loads ahead of the
+        // block computed while it is in flight)
+        const uint4 b0 = ld_snap(snap, jb.x), b1 = ld_snap(snap, jb.y), b2 = ld_snap(snap, jb.z),
+                    b3 = ld_snap(snap, jb.w);
+        jb = list_row(A, i, min(2 * (p + lpp) + 1, last));
+        __builtin_amdgcn_sched_barrier(0);
+        entry_fixed<P, EN, UNI>(xi, a0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, a1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, a2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, a3, c, pp, si, acc, e_sum, w_sum);
+        __builtin_amdgcn_sched_barrier(0);
+        a0 = ld_snap(snap, ja.x);
+        a1 = ld_snap(snap, ja.y);
+        a2 = ld_snap(snap, ja.z);
+        a3 = ld_snap(snap, ja.w);
+        ja = list_row(A, i, min(2 * (p + 2 * lpp), last));
+        __builtin_amdgcn_sched_barrier(0);
+        entry_fixed<P, EN, UNI>(xi, b0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, b1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, b2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, UNI>(xi, b3, c, pp, si, acc, e_sum, w_sum);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// FP64 path: double snapshots, textbook minimum image, FP64 pair term.
+__device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restrict__ snap, int i,
+                                          double xi, double yi, double zi, int si, const RepDev &r,
+                                          const PairDev &pp, double &fx, double &fy, double &fz,
+                                          bool en, double &e_sum, double &w_sum, int sub, int lpp)
+{
+    const int cnt = A.nbr_cnt[i];
+    const size_t P_ = (size_t)A.P;
+    const uint4 *__restrict__ snap1 = snap + P_;
+    fx = fy = fz = 0.0;
+    double rc2[2], sig2[2], e24[2];
+    rc2[0] = pp.rc2d[si * 2]; rc2[1] = pp.rc2d[si * 2 + 1];
+    sig2[0] = pp.sig2d[si * 2]; sig2[1] = pp.sig2d[si * 2 + 1];
+    e24[0] = pp.eps24d[si * 2]; e24[1] = pp.eps24d[si * 2 + 1];
+    const int nq = ((cnt + 7) >> 3) << 1;
+    for (int q = sub; q < nq; q += lpp) {
+        const int4 jj = list_row(A, i, q);
+        const int js[4] = {jj.x, jj.y, jj.z, jj.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = js[u]; // padding entries lie beyond the cutoff
+            double xj, yj, zj, wj;
+            u4_to_dbl2(snap[j], xj, yj);
+            u4_to_dbl2(snap1[j], zj, wj);
+            double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            dx -= r.L * rint(dx * r.invL);
+            dy -= r.L * rint(dy * r.invL);
+            dz -= r.L * rint(dz * r.invL);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            int b = meta_of_bits(wj) & 1;
+            double ir2 = 1.0 / r2;
+            double s2 = sig2[b] * ir2;
+            double s6 = s2 * s2 * s2;
+            double ff = e24[b] * ir2 * s6 * (2.0 * s6 - 1.0);
+            bool in = r2 < rc2[b];
+            ff = in ? ff : 0.0;
+            fx += ff * dx;
+            fy += ff * dy;
+            fz += ff * dz;
+            if (en && in) {
+                int tt = si * 2 + b;
+                e_sum += 0.5 * (pp.eps4d[tt] * s6 * (s6 - 1.0) - pp.shiftd[tt]);
+                w_sum += 0.5 * ff * r2;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ k_step
+enum { M_ADV = 0, M_FIN = 1, M_IDLE = 2 };
+
+template <int P, bool OBS, bool UNI, int LPP>
+__global__ void __launch_bounds__(1024) k_step(const StepArgs a)
+{
+    const KArena &A = a.A;
+    const int nblk = gridDim.x;
+    const int blk = remap_block(blockIdx.x, nblk, a.xcd);
+    const int gid = blk * blockDim.x + threadIdx.x;
+    const int i = gid / LPP;   // LPP adjacent lanes share particle i
+    const int sub = gid % LPP;
+    constexpr int NS = Traits<P>::NS;
+
+    if (!OBS) { // clear the other parity's cell counters and rebuild list (read
+                // by the previous step's rebuild)
+        const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+        for (int c = gt; c < a.cell_cap; c += nblk * blockDim.x) a.count_other[c] = 0;
+        if (gt == 0) a.rlist_other[0] = 0;
+    }
+    if (i >= A.P) return;
+
+    uint4 s0 = a.snap_cur[i];
+    uint4 s1;
+    uint32_t meta;
+    if (NS == 2) {
+        s1 = a.snap_cur[(size_t)A.P + i];
+        double zz, ww;
+        u4_to_dbl2(s1, zz, ww);
+        meta = meta_of_bits(ww);
+    } else {
+        meta = s0.w;
+    }
+    if (meta == NO_SLOT) return;
+    const int r = slot_of_meta(meta);
+    if (r >= a.max_slots) return;
+    const Ctl ctl = a.ctl_cur[r];
+    if (!ctl.z) return;
+    const RepDev rp = a.rep[r];
+    int mode;
+    if (OBS) {
+        mode = M_FIN;
+    } else {
+        const int tgt = a.target[r];
+        mode = ctl.x < tgt ? M_ADV : (ctl.y ? M_IDLE : M_FIN);
+        if (i == rp.off && sub == 0) { // the replica's first particle owns its control words
+            Ctl nx = ctl;
+            if (mode == M_ADV) { nx.x = ctl.x + 1; nx.y = 0; }
+            else nx.y = 1;
+            a.ctl_next[r] = nx;
+            a.need_other[r] = 0;
+        }
+        if (mode == M_IDLE) {
+            if (sub == 0) {
+                a.snap_next[i] = s0;
+                if (NS == 2) a.snap_next[(size_t)A.P + i] = s1;
+            }
+            return;
+        }
+    }
+    const int si = (int)(meta & SPECIES_MASK);
+    double e_sum = 0.0, w_sum = 0.0;
+    double fxd, fyd, fzd;
+
+    State<P> st;
+    st.load(A, i);
+
+    if constexpr (P == PREC_FP64) {
+        double xi, yi, zi, wi;
+        u4_to_dbl2(s0, xi, yi);
+        u4_to_dbl2(s1, zi, wi);
+        force_dbl(A, a.snap_cur, i, xi, yi, zi, si, rp, a.pp, fxd, fyd, fzd, OBS, e_sum, w_sum, sub, LPP);
+#pragma unroll
+        for (int m = 1; m < LPP; m <<= 1) {
+            lane_sum(fxd, m); lane_sum(fyd, m); lane_sum(fzd, m);
+            if (OBS) { lane_sum(e_sum, m); lane_sum(w_sum, m); }
+        }
+        if (sub != 0) return;
+        if (OBS) {
+            double *o = a.obs + (size_t)i * 8;
+            o[0] = fxd; o[1] = fyd; o[2] = fzd; o[3] = e_sum; o[4] = w_sum;
+            o[5] = st.vx; o[6] = st.vy; o[7] = st.vz;
+            return;
+        }
+        if (!ctl.y) kickd(st, fxd, fyd, fzd, a.ig);
+        if (mode == M_ADV) {
+            kickd(st, fxd, fyd, fzd, a.ig);
+            driftd(st, a.ig);
+        }
+    } else {
+        const LaneConsts c = lane_consts(a.pp, si, rp);
+        FAcc<P> acc;
+        force_fixed<P, OBS, UNI>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum, sub, LPP);
+        // combine the lanes' partial sums (a no-op for one lane per particle)
+        DsForce F;
+        if constexpr (P == PREC_DS) F = {acc.x.result(), acc.y.result(), acc.z.result()};
+#pragma unroll
+        for (int m = 1; m < LPP; m <<= 1) {
+            if constexpr (P == PREC_DS) { lane_sum(F.x, m); lane_sum(F.y, m); lane_sum(F.z, m); }
+            else { lane_sum(acc.x, m); lane_sum(acc.y, m); lane_sum(acc.z, m); }
+            if (OBS) { lane_sum(e_sum, m); lane_sum(w_sum, m); }
+        }
+        if (sub != 0) return;
+        if (OBS) {
+            if constexpr (P == PREC_DS) { fxd = ds_to_double(F.x); fyd = ds_to_double(F.y); fzd = ds_to_double(F.z); }
+            else acc.get(fxd, fyd, fzd);
+            double *o = a.obs + (size_t)i * 8;
+            o[0] = fxd; o[1] = fyd; o[2] = fzd; o[3] = e_sum; o[4] = w_sum;
+            double vx, vy, vz;
+            if constexpr (P == PREC_FP32) { vx = st.vx; vy = st.vy; vz = st.vz; }
+            else if constexpr (P == PREC_DS) { vx = ds_to_double(st.vx); vy = ds_to_double(st.vy); vz = ds_to_double(st.vz); }
+            else { vx = st.vx; vy = st.vy; vz = st.vz; }
+            o[5] = vx; o[6] = vy; o[7] = vz;
+            return;
+        }
+        if constexpr (P == PREC_FP32) {
+            if (!ctl.y) kick(st, acc, a.ig);
+            if (mode == M_ADV) { kick(st, acc, a.ig); drift(st, a.ig); }
+        } else if constexpr (P == PREC_DS) {
+            if (!ctl.y) kick(st, F, a.ig);
+            if (mode == M_ADV) { kick(st, F, a.ig); drift(st, a.ig); }
+        } else { // MIXED64: FP64 sum of FP32 pair terms
+            fxd = acc.x; fyd = acc.y; fzd = acc.z;
+            if (!ctl.y) kickd(st, fxd, fyd, fzd, a.ig);
+            if (mode == M_ADV) { kickd(st, fxd, fyd, fzd, a.ig); driftd(st, a.ig); }
+        }
+    }
+    st.store(A, i);
+    if (mode != M_ADV) { // finalised: positions unchanged
+        a.snap_next[i] = s0;
+        if (NS == 2) a.snap_next[(size_t)A.P + i] = s1;
+        return;
+    }
+
+    // new snapshot, displacement test, cell count
+    int cell;
+    bool far, bad;
+    if constexpr (P == PREC_FP64) {
+        double w = bits_of_meta(meta);
+        a.snap_next[i] = dbl2_to_u4(st.x, st.y);
+        a.snap_next[(size_t)A.P + i] = dbl2_to_u4(st.z, w);
+        double rx, ry, rz, rw;
+        u4_to_dbl2(A.xref[i], rx, ry);
+        u4_to_dbl2(A.xref[(size_t)A.P + i], rz, rw);
+        double dx = st.x - rx, dy = st.y - ry, dz = st.z - rz;
+        dx -= rp.L * rint(dx * rp.invL);
+        dy -= rp.L * rint(dy * rp.invL);
+        dz -= rp.L * rint(dz * rp.invL);
+        far = dx * dx + dy * dy + dz * dz > a.pp.hs2d;
+        bad = !isfinite(st.x + st.y + st.z);
+        cell = dbl_cell(st.x, st.y, st.z, rp.L, rp.invL, rp.nd);
+    } else {
+        uint4 X = snap_of(st, rp, meta);
+        a.snap_next[i] = X;
+        uint4 R = A.xref[i];
+        float dx = (float)(int)(X.x - R.x), dy = (float)(int)(X.y - R.y), dz = (float)(int)(X.z - R.z);
+        float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        float thr = (float)(a.pp.hs2d / ((double)rp.sc * (double)rp.sc));
+        far = d2 > thr;
+        if constexpr (P == PREC_FP32) bad = !isfinite(st.x + st.y + st.z);
+        else if constexpr (P == PREC_DS) bad = !isfinite(st.x.hi + st.y.hi + st.z.hi);
+        else bad = !isfinite(st.x + st.y + st.z);
+        cell = rp.nd == 1 ? 0 : fixed_cell(X.x, X.y, X.z, rp.nd);
+    }
+    atomicAdd(a.count_cur + rp.coff + cell, 1);
+    if (far && atomicOr(a.need_cur + r, 1) == 0) { // first to flag: enlist the slot
+        const int k = atomicAdd(a.rlist_cur, 1);
+        a.rlist_cur[1 + k] = r;
+    }
+    if (bad) atomicOr(a.status + r, 2);
+}
+
+// ------------------------------------------------------------ launcher
+template <int P, int LPP>
+static hipError_t launch_step_l(const StepArgs &a, int block, bool obs, hipStream_t s)
+{
+    const long long threads = (long long)a.A.P * LPP;
+    const int grid = (int)((threads + block - 1) / block);
+    const bool uni = a.pp.uniform != 0 && P != PREC_FP64;
+    if (obs && uni) hipLaunchKernelGGL((k_step<P, true, true, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else if (obs) hipLaunchKernelGGL((k_step<P, true, false, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else if (uni) hipLaunchKernelGGL((k_step<P, false, true, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, false, false, LPP>), dim3(grid), dim3(block), 0, s, a);
+    LAUNCH_CHECK();
+}
+
+template <int P>
+static hipError_t launch_step_t(const StepArgs &a, int block, bool obs, hipStream_t s)
+{
+    if (a.lpp == 4) return launch_step_l<P, 4>(a, block, obs, s);
+    if (a.lpp == 2) return launch_step_l<P, 2>(a, block, obs, s);
+    return launch_step_l<P, 1>(a, block, obs, s);
+}
+
+hipError_t launch_step(int prec, const StepArgs &a, int block, bool obs, hipStream_t s)
+{
+    switch (prec) {
+    case PREC_FP32: return launch_step_t<PREC_FP32>(a, block, obs, s);
+    case PREC_DS: return launch_step_t<PREC_DS>(a, block, obs, s);
+    case PREC_MIX: return launch_step_t<PREC_MIX>(a, block, obs, s);
+    default: return launch_step_t<PREC_FP64>(a, block, obs, s);
+    }
+}

@@ -25,10 +25,10 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device sources: counter summaries taken on other sources
-    are stale."""
+    """Hash of the sources the fused step kernel is compiled from: counter
+    summaries taken on other sources are stale."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "md_dev.hpp", "ds.hpp", "kernels.hpp"):
+    for f in ("step.hip", "dev_common.hpp", "md_dev.hpp", "ds.hpp", "kernels.hpp"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -22,8 +22,6 @@
 namespace {
 
 constexpr int64_t ALIGN = 256;
-constexpr int GRID_PERM = 2048;   // persistent grids of the rebuild kernels
-constexpr int GRID_BUILD = 1024;
 constexpr uint32_t CKPT_MAGIC = 0x4d445843; // "MDXC"
 constexpr int CKPT_VERSION = 2;
 constexpr int MD_DEFAULT_LPP = 2;
@@ -110,6 +108,8 @@ struct md_system {
     RangeAlloc parena, carena;
     int parity = 0; // parity of the snapshot the next step reads
     int lpp = 1;    // lanes per particle of the force sum
+    int n_cu = 0;   // compute units of the device
+    int grid_perm = 0, grid_build = 0; // one full residency of the rebuild kernels
     std::map<int, hipGraphExec_t> graphs;
     std::string err;
 };
@@ -308,6 +308,23 @@ static int cells_per_edge(double L, double rl)
     return nd;
 }
 
+// staged candidates per list-build workgroup (48 KB of LDS)
+static int lds_cap_of(int prec) { return prec == PREC_FP64 ? 1536 : 3072; }
+
+// Grids of the sort and list-build kernels: one full residency of the
+// device (queried for the current block size).
+static md_status size_grids(md_system *s)
+{
+    int per_cu = 0;
+    HIPCHK(s, occupancy_permute(s->prec, &per_cu));
+    s->grid_perm = std::max(1, per_cu) * s->n_cu;
+    per_cu = 0;
+    HIPCHK(s, occupancy_build(s->prec, s->launch.build_block, lds_cap_of(s->prec), &per_cu));
+    if (per_cu < 1) return fail(s, MD_E_ARG, "list-build block of %d threads does not fit a CU", s->launch.build_block);
+    s->grid_build = per_cu * s->n_cu;
+    return MD_OK;
+}
+
 // members per list-build work item of a single-cell replica: one group of
 // build_lanes lanes (16 when automatic) per member
 static int single_members(const md_system *s)
@@ -460,7 +477,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     pa.sc_snap = s->sc_snap;
     pa.sc_meta = s->sc_meta;
     pa.status = s->status;
-    HIPCHK(s, launch_permute(prec, pa, GRID_PERM, s->stream));
+    HIPCHK(s, launch_permute(prec, pa, s->grid_perm, s->stream));
 
     BuildArgs ba;
     memset(&ba, 0, sizeof ba);
@@ -469,7 +486,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     ba.force_slot = force_slot;
     ba.from_scratch = from_scratch ? 1 : 0;
     ba.width = s->launch.build_width;
-    ba.lds_cap = prec == PREC_FP64 ? 1536 : 3072;
+    ba.lds_cap = lds_cap_of(prec);
     ba.single_members = single_members(s);
     ba.xcd = s->launch.xcd_remap;
     ba.items_pref = s->items4;
@@ -485,7 +502,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     ba.sc_meta = s->sc_meta;
     ba.status = s->status;
     ba.pp = s->pp;
-    HIPCHK(s, launch_build(prec, ba, GRID_BUILD, s->launch.build_block, s->stream));
+    HIPCHK(s, launch_build(prec, ba, s->grid_build, s->launch.build_block, s->stream));
     return MD_OK;
 }
 
@@ -499,7 +516,7 @@ static md_status launch_build_main(md_system *s, int slot)
     ba.force_slot = slot;
     ba.from_scratch = 0;
     ba.width = s->launch.build_width;
-    ba.lds_cap = s->prec == PREC_FP64 ? 1536 : 3072;
+    ba.lds_cap = lds_cap_of(s->prec);
     ba.single_members = single_members(s);
     ba.xcd = s->launch.xcd_remap;
     ba.items_pref = s->items4;
@@ -513,7 +530,7 @@ static md_status launch_build_main(md_system *s, int slot)
     ba.snap_cur = s->snap[0];
     ba.status = s->status;
     ba.pp = s->pp;
-    HIPCHK(s, launch_build(s->prec, ba, GRID_BUILD, s->launch.build_block, s->stream));
+    HIPCHK(s, launch_build(s->prec, ba, s->grid_build, s->launch.build_block, s->stream));
     return MD_OK;
 }
 
@@ -836,6 +853,15 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     s->launch.xcd_remap = 0;
     s->launch.build_lanes = 0;
     make_tables(s);
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            size_grids(s) != MD_OK) {
+            delete s;
+            return MD_E_HIP;
+        }
+    }
     s->slots.assign(L.slots, SlotHost());
     s->parena.reset(L.P);
     s->carena.reset(L.cells);
@@ -1466,8 +1492,17 @@ md_status md_set_launch(md_system *s, const md_launch *in)
     if (l.graph_steps != 0 && (l.graph_steps < 2 || l.graph_steps > 256 || l.graph_steps % 2))
         return fail(s, MD_E_ARG, "bad graph_steps");
     drop_graphs(s);
+    const md_launch prev = s->launch;
     s->launch = l;
     s->launch.xcd_remap = l.xcd_remap ? 1 : 0;
+    const md_status gs = size_grids(s);
+    if (gs != MD_OK) {
+        const std::string why = s->err;
+        s->launch = prev;
+        (void)size_grids(s);
+        s->err = why;
+        return gs;
+    }
     // refresh per-slot item counts (list-build items depend on the shapes)
     for (int k = 0; k < (int)s->lay.slots; ++k)
         if (s->slots[k].attached) {

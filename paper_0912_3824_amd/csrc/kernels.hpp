@@ -113,6 +113,8 @@ hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
 hipError_t launch_permute(int prec, const PermArgs &a, int grid, hipStream_t s);
 hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipStream_t s);
+hipError_t occupancy_permute(int prec, int *per_cu);
+hipError_t occupancy_build(int prec, int block, int lds_cap, int *per_cu);
 hipError_t launch_obs_reduce(const ObsArgs &a, hipStream_t s);
 hipError_t launch_scale_vel(int prec, const ScaleArgs &a, hipStream_t s);
 hipError_t launch_ds_eval(int op, long long n, const float *a, const float *b, float *out, hipStream_t s);

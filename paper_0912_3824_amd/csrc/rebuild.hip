@@ -324,17 +324,24 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
     int *col = A.nbr_w + 4 * (size_t)i;
     const size_t row_stride = 4 * P_;
     int cnt = 0;
-    int *wp = col; // where entry cnt goes
-    auto test = [&](int e, int st) -> bool {
+    // a candidate's snapshot (two words for double snapshots), then the test
+    struct Cand { uint4 a, b; };
+    auto load = [&](int e, int st) -> Cand {
+        Cand q;
+        if (NS == 2) {
+            q.a = FROM_LDS ? cand[2 * (st + e)] : a.src_x[st + e];
+            q.b = FROM_LDS ? cand[2 * (st + e) + 1] : a.src_x[P_ + st + e];
+        } else {
+            q.a = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+            q.b = q.a;
+        }
+        return q;
+    };
+    auto eval = [&](const Cand &q) -> bool {
         if (NS == 2) {
             double xj, yj, zj, wj;
-            if (FROM_LDS) {
-                u4_to_dbl2(cand[2 * (st + e)], xj, yj);
-                u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
-            } else {
-                u4_to_dbl2(a.src_x[st + e], xj, yj);
-                u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
-            }
+            u4_to_dbl2(q.a, xj, yj);
+            u4_to_dbl2(q.b, zj, wj);
             double dx = xd - xj, dy = yd - yj, dz = zd - zj;
             dx -= rp.L * rint(dx * rp.invL);
             dy -= rp.L * rint(dy * rp.invL);
@@ -342,35 +349,43 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             const double r2 = dx * dx + dy * dy + dz * dz;
             return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
         }
-        const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+        const uint4 xj = q.a;
         const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
                     dz = (float)(int)(xi.z - xj.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
         return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
     };
-    // Candidates of one cell in slot order; accepted ones are stored at once
-    // (a predicated 4-byte store).  `self` is the candidate index of i in
-    // this cell, or -1.
-    auto put = [&](bool acc, int j) {
-        if (acc) {
-            if (cnt < cap) *wp = j;
-            ++cnt;
-            wp += (cnt & 3) ? 1 : (ptrdiff_t)row_stride - 3;
-        }
-    };
-    // four candidates per iteration: independent reads and tests in flight
-    // (the scan is a dependent chain per member), stores in slot order
+    auto test = [&](int e, int st) -> bool { return eval(load(e, st)); };
+    // Candidates of one cell in slot order; `self` is the candidate index of
+    // i in this cell, or -1.  Each chunk of up to 64 candidates is tested
+    // four at a time (independent reads in flight, no stores and no branches
+    // in the test loop: a wave would otherwise run the store path whenever
+    // any of its lanes accepts) into an acceptance mask, whose set bits are
+    // then stored in slot order.
     auto scan_cell = [&](int k, int self) {
         const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
-        int e = 0;
-        for (; e + 4 <= n; e += 4) {
-            const bool c0 = test(e, st), c1 = test(e + 1, st), c2 = test(e + 2, st), c3 = test(e + 3, st);
-            put(c0 && e != self, g0 + e);
-            put(c1 && e + 1 != self, g0 + e + 1);
-            put(c2 && e + 2 != self, g0 + e + 2);
-            put(c3 && e + 3 != self, g0 + e + 3);
+        for (int base = 0; base < n; base += 64) {
+            const int m = min(64, n - base), last = base + m - 1;
+            unsigned long long mask = 0;
+            for (int e = 0; e < m; e += 4) {
+                // past the chunk's end: re-test its last candidate, masked off
+                const Cand q0 = load(base + e, st), q1 = load(min(base + e + 1, last), st),
+                           q2 = load(min(base + e + 2, last), st), q3 = load(min(base + e + 3, last), st);
+                const bool c0 = eval(q0);
+                const bool c1 = eval(q1) && e + 1 < m;
+                const bool c2 = eval(q2) && e + 2 < m;
+                const bool c3 = eval(q3) && e + 3 < m;
+                const unsigned bits = (unsigned)c0 | ((unsigned)c1 << 1) | ((unsigned)c2 << 2) | ((unsigned)c3 << 3);
+                mask |= (unsigned long long)bits << e;
+            }
+            if (self >= base && self < base + 64) mask &= ~(1ull << (self - base));
+            while (mask) {
+                const int b = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                if (cnt < cap) col[4 * ((unsigned long long)(unsigned)(cnt >> 2) * (unsigned)P_) + (cnt & 3)] = g0 + base + b;
+                ++cnt;
+            }
         }
-        for (; e < n; ++e) put(test(e, st) && e != self, g0 + e);
     };
     int last_cell = 0;
     if (nd == 1) {
@@ -486,9 +501,9 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
         for (int b = 0; b < c.y; b += 4 * G) {
             bool acc[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 4; ++u) { // past the end: test the last candidate, masked off
                 const int e = b + u * G + gl;
-                acc[u] = e < c.y && test(e, c.x) && c.z + e != i;
+                acc[u] = test(min(e, c.y - 1), c.x) && e < c.y && c.z + e != i;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -744,6 +759,35 @@ hipError_t launch_permute(int prec, const PermArgs &a, int grid, hipStream_t s)
     default: hipLaunchKernelGGL((k_permute<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
     }
     LAUNCH_CHECK();
+}
+
+// Resident workgroups per CU of the sort and list-build kernels (their grids
+// are sized to one full residency: the kernels walk their work items in a
+// grid-stride loop, and a second partial round of workgroups would idle most
+// of the chip while it runs).
+hipError_t occupancy_permute(int prec, int *per_cu)
+{
+    const void *f;
+    switch (prec) {
+    case PREC_FP32: f = (const void *)k_permute<PREC_FP32>; break;
+    case PREC_DS: f = (const void *)k_permute<PREC_DS>; break;
+    case PREC_MIX: f = (const void *)k_permute<PREC_MIX>; break;
+    default: f = (const void *)k_permute<PREC_FP64>; break;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, 256, 0);
+}
+
+hipError_t occupancy_build(int prec, int block, int lds_cap, int *per_cu)
+{
+    const size_t lds = (size_t)lds_cap * 16 * (prec == PREC_FP64 ? 2 : 1);
+    const void *f;
+    switch (prec) {
+    case PREC_FP32: f = (const void *)k_build<PREC_FP32>; break;
+    case PREC_DS: f = (const void *)k_build<PREC_DS>; break;
+    case PREC_MIX: f = (const void *)k_build<PREC_MIX>; break;
+    default: f = (const void *)k_build<PREC_FP64>; break;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, block, lds);
 }
 
 hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipStream_t s)

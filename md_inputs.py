@@ -42,6 +42,7 @@ class PairTable:
     eps: np.ndarray     # [2,2]
     sigma: np.ndarray   # [2,2]
     rcut: np.ndarray    # [2,2]
+    smooth: float = 0.0 # h of the C2 smoothing factor (0 = none)
 
     def max_rcut(self) -> float:
         k = self.n_species

@@ -17,7 +17,13 @@
  *       v += dt/(2m) F;  r += dt v;  wrap r into [0, L);  F = F(r);
  *       v += dt/(2m) F;
  *   - neighbour-list membership (Sec. 2.2: every particle within the cutoff
- *     plus a skin): j in L_i  iff  j != i and |d_ij| < rc_{s_i s_j} + skin.
+ *     plus a skin): j in L_i  iff  j != i and |d_ij| < rc_{s_i s_j} + skin;
+ *   - optional C2 smoothing (Sec. 4, numerical long-time stability): the
+ *     truncated-and-shifted potential times g(x) = x^4 / (1 + x^4) with
+ *     x = (r - rc_ab) / (h sigma_ab); h = 0 means no smoothing.  The purely
+ *     repulsive WCA potential of the same section is LJ cut at
+ *     rc = 2^(1/6) sigma with the energy shifted by +eps, which the shifted
+ *     truncation gives for that cutoff.
  *
  * Everything is double precision; OpenMP parallelises over i only (each i is
  * an independent sum in a fixed j order).
@@ -72,17 +78,34 @@ static void min_image(const double *ri, const double *rj, double L, double d[3])
     }
 }
 
-/* Pair energy (shifted) and force factor; zero at and beyond the cutoff. */
-void orc_pair(double r2, double eps, double sig, double rc, double *v_shifted,
-              double *ff)
+/*
+ * Pair energy (shifted; smoothed when h > 0) and force factor ff with
+ * F_vec = ff * d_vec; both zero at and beyond the cutoff.  Smoothing:
+ *   V_s(r) = V_ts(r) g(x),  x = (r - rc) / (h sig),  g(x) = x^4 / (1 + x^4)
+ *   -dV_s/dr = (-dV_ts/dr) g(x) - V_ts(r) g'(x) / (h sig),
+ *   g'(x) = 4 x^3 / (1 + x^4)^2.
+ */
+void orc_pair(double r2, double eps, double sig, double rc, double h,
+              double *v_shifted, double *ff)
 {
-    if (r2 < rc * rc) {
-        *v_shifted = lj_v(r2, eps, sig) - lj_v(rc * rc, eps, sig);
-        *ff = lj_ff(r2, eps, sig);
-    } else {
+    if (!(r2 < rc * rc)) {
         *v_shifted = 0.0;
         *ff = 0.0;
+        return;
     }
+    double v = lj_v(r2, eps, sig) - lj_v(rc * rc, eps, sig);
+    double f = lj_ff(r2, eps, sig); /* (-dV/dr) / r */
+    if (h > 0.0) {
+        double r = sqrt(r2);
+        double x = (r - rc) / (h * sig);
+        double x2 = x * x, x4 = x2 * x2;
+        double g = x4 / (1.0 + x4);
+        double dg = 4.0 * x2 * x / ((1.0 + x4) * (1.0 + x4));
+        f = f * g - v * dg / (h * sig) / r;
+        v = v * g;
+    }
+    *v_shifted = v;
+    *ff = f;
 }
 
 /*
@@ -94,7 +117,7 @@ void orc_pair(double r2, double eps, double sig, double rc, double *v_shifted,
  */
 void orc_forces(int n, double L, const int *species, const double *pos,
                 int n_species, const double *eps, const double *sig,
-                const double *rc, const int *sel, int m, double *f,
+                const double *rc, double h, const int *sel, int m, double *f,
                 double *e_i, double *w_i)
 {
     orc_table t;
@@ -112,7 +135,7 @@ void orc_forces(int n, double L, const int *species, const double *pos,
             min_image(pos + 3 * i, pos + 3 * j, L, d);
             double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             double v, ff;
-            orc_pair(r2, t.eps[si][sj], t.sig[si][sj], t.rc[si][sj], &v, &ff);
+            orc_pair(r2, t.eps[si][sj], t.sig[si][sj], t.rc[si][sj], h, &v, &ff);
             fx += ff * d[0];
             fy += ff * d[1];
             fz += ff * d[2];
@@ -171,15 +194,16 @@ void orc_neighbours(int n, double L, const int *species, const double *pos,
  */
 void orc_vv(int n, double L, const int *species, double *pos, double *vel,
             int *image, int n_species, const double *eps, const double *sig,
-            const double *rc, double mass, double dt, int steps, double *f_out)
+            const double *rc, double h, double mass, double dt, int steps,
+            double *f_out)
 {
     double *f = (double *)malloc(sizeof(double) * 3 * (size_t)n);
-    orc_forces(n, L, species, pos, n_species, eps, sig, rc, NULL, n, f, NULL,
+    orc_forces(n, L, species, pos, n_species, eps, sig, rc, h, NULL, n, f, NULL,
                NULL);
-    double h = 0.5 * dt / mass;
+    double hk = 0.5 * dt / mass; /* half-kick factor */
     for (int s = 0; s < steps; ++s) {
         for (int i = 0; i < 3 * n; ++i) {
-            vel[i] += h * f[i];
+            vel[i] += hk * f[i];
             pos[i] += dt * vel[i];
             double k = floor(pos[i] / L);
             pos[i] -= k * L;
@@ -194,10 +218,10 @@ void orc_vv(int n, double L, const int *species, double *pos, double *vel,
             if (image)
                 image[i] += (int)k;
         }
-        orc_forces(n, L, species, pos, n_species, eps, sig, rc, NULL, n, f,
+        orc_forces(n, L, species, pos, n_species, eps, sig, rc, h, NULL, n, f,
                    NULL, NULL);
         for (int i = 0; i < 3 * n; ++i)
-            vel[i] += h * f[i];
+            vel[i] += hk * f[i];
     }
     if (f_out)
         memcpy(f_out, f, sizeof(double) * 3 * (size_t)n);

@@ -7,7 +7,8 @@ definition for tiny systems.
 
 What it computes is the plain definition of the paper's MD step (Sec. 2.2,
 velocity Verlet with short-ranged pair forces; Sec. 3 LJ 12-6 cut at
-rc = 2.5 sigma; Sec. 5 Kob-Andersen pair table): brute-force forces, energies
+rc = 2.5 sigma; Sec. 5 Kob-Andersen pair table; Sec. 4 WCA and the C2
+smoothing factor g): brute-force forces, energies
 and virials, brute-force neighbour-list membership, and a naive
 velocity-Verlet integrator.  Parity status of each function is listed in the
 design notes; every function here is pinned by a test against a fact that
@@ -49,15 +50,16 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         lib.orc_forces.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp, ctypes.c_int,
-                                   dp, dp, dp, ip, ctypes.c_int, dp, dp, dp]
+                                   dp, dp, dp, ctypes.c_double, ip, ctypes.c_int, dp, dp, dp]
         lib.orc_forces.restype = None
         lib.orc_neighbours.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp, ctypes.c_int,
                                        dp, ip, ctypes.c_int, ctypes.c_int, ip, ip]
         lib.orc_neighbours.restype = None
         lib.orc_vv.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp, dp, ip, ctypes.c_int,
-                               dp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+                               dp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int, dp]
         lib.orc_vv.restype = None
-        lib.orc_pair.argtypes = [ctypes.c_double] * 4 + [dp, dp]
+        lib.orc_pair.argtypes = [ctypes.c_double] * 5 + [dp, dp]
         lib.orc_pair.restype = None
         _lib = lib
     return _lib
@@ -78,13 +80,15 @@ def _tab(table):
     return eps, sig, rc
 
 
-def pair(r: float, eps: float = 1.0, sigma: float = 1.0, rc: float = 2.5) -> Tuple[float, float]:
-    """(V_ts(r), F(r)) for one pair at distance r: truncated-and-shifted
-    energy and the radial force -dV/dr (positive = repulsive)."""
+def pair(r: float, eps: float = 1.0, sigma: float = 1.0, rc: float = 2.5,
+         h: float = 0.0) -> Tuple[float, float]:
+    """(V(r), F(r)) for one pair at distance r: truncated-and-shifted energy
+    (times the smoothing factor g when h > 0) and the radial force -dV/dr
+    (positive = repulsive)."""
     lib = _load()
     v = ctypes.c_double()
     ff = ctypes.c_double()
-    lib.orc_pair(r * r, eps, sigma, rc, ctypes.byref(v), ctypes.byref(ff))
+    lib.orc_pair(r * r, eps, sigma, rc, h, ctypes.byref(v), ctypes.byref(ff))
     return v.value, ff.value * r
 
 
@@ -108,7 +112,7 @@ def forces(pos: np.ndarray, box: float, species: np.ndarray, table,
     e = np.zeros(m)
     w = np.zeros(m)
     lib.orc_forces(n, box, _i(sp), _d(pos), table.n_species, _d(eps), _d(sig), _d(rc),
-                   selp, m, _d(f), _d(e), _d(w))
+                   float(table.smooth), selp, m, _d(f), _d(e), _d(w))
     return f, e, w
 
 
@@ -148,7 +152,7 @@ def vv(pos: np.ndarray, vel: np.ndarray, box: float, species: np.ndarray, table,
     eps, sig, rc = _tab(table)
     f = np.zeros((n, 3))
     lib.orc_vv(n, box, _i(sp), _d(p), _d(v), _i(img), table.n_species, _d(eps), _d(sig),
-               _d(rc), mass, dt, steps, _d(f))
+               _d(rc), float(table.smooth), mass, dt, steps, _d(f))
     return p, v, img, f
 
 
@@ -187,5 +191,15 @@ def forces_numpy(pos: np.ndarray, box: float, species: np.ndarray, table):
     s6c = (sig * sig / (rc * rc)) ** 3
     v = np.where(inside, 4 * eps * (s6 * s6 - s6) - 4 * eps * (s6c * s6c - s6c), 0.0)
     ff = np.where(inside, 24 * eps * (2 * s6 * s6 - s6) / r2, 0.0)
+    h = float(table.smooth)
+    if h > 0:
+        with np.errstate(invalid="ignore", divide="ignore"):
+            r = np.sqrt(r2)
+            x = (r - rc) / (h * sig)
+            x4 = x ** 4
+            g = x4 / (1 + x4)
+            dg = 4 * x ** 3 / (1 + x4) ** 2
+            ff = np.where(inside, ff * g - v * dg / (h * sig) / r, 0.0)
+            v = np.where(inside, v * g, 0.0)
     f = np.sum(ff[:, :, None] * d, axis=1)
     return f, 0.5 * v.sum(axis=1), 0.5 * (ff * r2).sum(axis=1)

@@ -301,3 +301,117 @@ def test_generated_velocities_have_exact_temperature():
     assert T == pytest.approx(0.55, rel=1e-13)
     assert np.abs(s.vel.sum(axis=0)).max() < 1e-11
     assert int((s.species == 0).sum()) == 800
+
+
+# ---------------------------------------------------------------- smoothing
+# Sec. 4: the potential times g(x) = x^4 / (1 + x^4), x = (r - rc) / (h sigma).
+
+def _lj_exact(r2, eps, sig):
+    """4 eps [(sig^2/r^2)^6 - (sig^2/r^2)^3] in exact rationals."""
+    from fractions import Fraction as Fr
+    s2 = Fr(sig) ** 2 / r2
+    return 4 * Fr(eps) * (s2 ** 6 - s2 ** 3)
+
+
+@pytest.mark.parametrize("eps,sig,h", [(1.0, 1.0, 0.005), (1.5, 0.8, 0.01), (0.5, 0.88, 0.02)])
+def test_smoothing_at_one_width_inside_the_cutoff(eps, sig, h):
+    """At r = rc - h sigma, x = -1: g = 1/2 and g' = -1, so V_s = V_ts / 2 and
+    -dV_s/dr = F / 2 + V_ts / (h sigma).  Expected values in exact rationals
+    from the LJ formula (catches a wrong power, sign or width in g)."""
+    from fractions import Fraction as Fr
+    rc = 2.5 * sig
+    r = rc - h * sig
+    R = Fr(r)
+    vts = _lj_exact(R * R, eps, sig) - _lj_exact(Fr(rc) ** 2, eps, sig)
+    s2 = Fr(sig) ** 2 / (R * R)
+    f_lj = 24 * Fr(eps) * (2 * s2 ** 6 - s2 ** 3) / R
+    v, f = O.pair(r, eps, sig, rc, h)
+    assert v == pytest.approx(float(vts / 2), rel=1e-9)
+    assert f == pytest.approx(float(f_lj / 2 + vts / (Fr(h) * Fr(sig))), rel=1e-7)
+
+
+def test_smoothing_far_inside_and_at_ten_widths():
+    """x = -10: g = 10^4 / (1 + 10^4) exactly; deep inside, V_s -> V_ts."""
+    rc, h = 2.5, 0.01
+    r = rc - 10 * h
+    v_s, _ = O.pair(r, 1.0, 1.0, rc, h)
+    v_t, _ = O.pair(r, 1.0, 1.0, rc, 0.0)
+    assert v_s == pytest.approx(v_t * 1e4 / (1 + 1e4), rel=1e-9)
+    v_s, f_s = O.pair(1.1, 1.0, 1.0, rc, h)
+    v_t, f_t = O.pair(1.1, 1.0, 1.0, rc, 0.0)
+    x = (1.1 - rc) / h
+    assert v_s == pytest.approx(v_t, rel=2.0 / x ** 4)
+    assert f_s == pytest.approx(f_t, rel=1e-6)
+
+
+@pytest.mark.parametrize("h", [0.005, 0.01])
+def test_smoothed_potential_is_c2_at_the_cutoff(h):
+    """C2 at rc (why the paper smooths): approaching rc from inside, V_s
+    vanishes like delta^5 and the force like delta^4 (V_ts is linear in delta
+    and g like delta^4), whereas the plain truncated force jumps."""
+    rc = 2.5
+    d1, d2 = 0.02 * h, 0.01 * h
+    v1, f1 = O.pair(rc - d1, 1.0, 1.0, rc, h)
+    v2, f2 = O.pair(rc - d2, 1.0, 1.0, rc, h)
+    assert v1 / v2 == pytest.approx(32.0, rel=0.02)
+    assert f1 / f2 == pytest.approx(16.0, rel=0.02)
+    assert abs(f2) < 1e-6
+    assert O.pair(rc - d2, 1.0, 1.0, rc, 0.0)[1] == pytest.approx(-0.0389994774528, rel=5e-4)
+    assert O.pair(rc, 1.0, 1.0, rc, h) == (0.0, 0.0)
+
+
+def test_smoothed_force_is_minus_dv_dr():
+    """-dV_s/dr by 4th-order central differences, including the smoothing
+    region (catches a dropped product-rule term)."""
+    rng = np.random.default_rng(2)
+    for eps, sig, h in [(1.0, 1.0, 0.005), (1.5, 0.8, 0.01), (0.5, 0.88, 0.05)]:
+        rc = 2.5 * sig
+        rs = np.concatenate([rng.uniform(0.9 * sig, rc - 5 * h * sig, 10),
+                             rc - h * sig * rng.uniform(0.2, 4.0, 10)])
+        for r in rs:
+            dr = 1e-3 * h * sig
+            vs = [O.pair(r + k * dr, eps, sig, rc, h)[0] for k in (-2, -1, 1, 2)]
+            dv = (vs[0] - 8 * vs[1] + 8 * vs[2] - vs[3]) / (12 * dr)
+            f = O.pair(r, eps, sig, rc, h)[1]
+            assert f == pytest.approx(-dv, rel=1e-5, abs=1e-9 / (h * sig))
+
+
+@pytest.mark.parametrize("h", [0.0, 0.005])
+def test_wca_closed_forms(h):
+    """WCA (Sec. 4): LJ cut at 2^(1/6) sigma, shifted by +eps, so V(sigma) = eps,
+    V and F vanish at the cutoff, and the force is repulsive everywhere."""
+    rc = RMIN
+    v, f = O.pair(1.0, 1.0, 1.0, rc, h)
+    x = (1.0 - rc) / h if h else -np.inf
+    g = x ** 4 / (1 + x ** 4) if h else 1.0
+    assert v == pytest.approx(1.0 * g, rel=1e-12)
+    assert f == pytest.approx(24.0 * g, rel=1e-4)
+    v, f = O.pair(rc * (1 - 1e-9), 1.0, 1.0, rc, h)
+    assert abs(v) < 1e-12 and abs(f) < 1e-6
+    for r in np.linspace(0.85, rc * (1 - 1e-6), 40):
+        assert O.pair(r, 1.0, 1.0, rc, h)[1] > 0.0
+
+
+def test_smoothing_makes_energy_error_second_order():
+    """Sec. 4.3: velocity Verlet's energy error is O(dt^2) only for a
+    potential with a continuous second derivative.  With a short cutoff
+    (rc = 1.5 sigma, a large force jump) the plain truncation breaks the
+    dt^2 scaling of E(t) - E(0); the C2-smoothed potential restores a ratio
+    of 4 when dt is halved."""
+    base = I.make_lj(256, rho=0.75, temperature=1.12, jitter=0.05, seed=6)
+    span = 1.0
+    ratios = {}
+    for h in (0.0, 0.05):
+        t = I.PairTable(1, base.table.eps, base.table.sigma, np.full((2, 2), 1.5), smooth=h)
+        amp = []
+        for dt in (0.004, 0.002):
+            p, v = base.pos, base.vel
+            e0 = O.observables(p, v, base.box, base.species, t)["etot"]
+            dev = 0.0
+            for _ in range(20):
+                p, v, _, _ = O.vv(p, v, base.box, base.species, t, dt, int(round(span / dt / 20)))
+                dev = max(dev, abs(O.observables(p, v, base.box, base.species, t)["etot"] - e0))
+            amp.append(dev)
+        ratios[h] = amp[0] / amp[1]
+    assert 3.8 < ratios[0.05] < 4.2, ratios
+    assert abs(ratios[0.0] - 4.0) > 1.0, ratios

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 1
+#define MD_ABI_VERSION 2
 
 typedef struct md_system md_system;
 
@@ -110,6 +110,10 @@ typedef struct {
                                    combined in a fixed order, so results are
                                    bitwise reproducible for a given value. */
     int32_t reserved;
+    double smooth;         /* h of the C2 smoothing of Sec. 4: the truncated-and-
+                              shifted potential times g(x) = x^4 / (1 + x^4),
+                              x = (r - rc_ab) / (h sigma_ab); 0 = no smoothing;
+                              >= 0 and finite.  (WCA is rcut = 2^(1/6) sigma.) */
 } md_config;
 
 /* One replica: N particles in a cubic box of edge `box`. */

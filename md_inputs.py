@@ -49,11 +49,21 @@ class PairTable:
         return float(self.rcut[:k, :k].max())
 
 
-def lj_table(rc: float = 2.5) -> PairTable:
-    """Single-species LJ, eps = sigma = 1, cutoff rc (Sec. 3)."""
+def lj_table(rc: float = 2.5, smooth: float = 0.0) -> PairTable:
+    """Single-species LJ, eps = sigma = 1, cutoff rc (Sec. 3); rc = 2^(1/6)
+    gives the WCA potential of Sec. 4; `smooth` is the width h of its C2
+    smoothing."""
     e = np.ones((2, 2))
     s = np.ones((2, 2))
-    return PairTable(1, e, s, np.full((2, 2), rc))
+    return PairTable(1, e, s, np.full((2, 2), rc), smooth=smooth)
+
+
+WCA_RC = 2.0 ** (1.0 / 6.0)
+
+
+def smoothed(system: "System", h: float) -> "System":
+    """The same replica with the pair table's smoothing width set to h."""
+    return dataclasses.replace(system, table=dataclasses.replace(system.table, smooth=h))
 
 
 def ka_table(rc_over_sigma: float = 2.5) -> PairTable:

@@ -179,6 +179,7 @@ static md_status validate_cfg(const md_config *c, std::string *why)
     if (c->lanes_per_particle != 0 && c->lanes_per_particle != 1 && c->lanes_per_particle != 2 &&
         c->lanes_per_particle != 4)
         return bad("lanes_per_particle must be 0, 1, 2 or 4");
+    if (!(c->smooth >= 0) || !std::isfinite(c->smooth)) return bad("smooth must be >= 0 and finite");
     return MD_OK;
 }
 
@@ -273,7 +274,10 @@ static void make_tables(md_system *s)
         p.eps24[t] = (float)p.eps24d[t];
         p.eps4[t] = (float)p.eps4d[t];
         p.shift[t] = (float)p.shiftd[t];
+        p.hsd[t] = c->smooth * sig;
+        p.rcd[t] = rc;
     }
+    p.smooth = c->smooth > 0 ? 1 : 0;
     // uniform cutoff ratio: rc_ab / sigma_ab equal (to rounding) for every pair
     {
         const int k = c->n_species;

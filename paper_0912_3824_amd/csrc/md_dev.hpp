@@ -66,6 +66,9 @@ struct PairDev {
     int nsp;
     int uniform;     // 1 if rc_ab / sigma_ab is the same for every pair
     float s2cut;     // then (sigma_ab / rc_ab)^2: a pair is inside iff sigma^2/r^2 > s2cut
+    int smooth;      // 1: potential times g(x) = x^4/(1+x^4), x = (r - rc)/(h sigma) (Sec. 4)
+    double hsd[4];   // h sigma_ab
+    double rcd[4];   // rc_ab
 };
 
 // Integration constants (dt and dt/2m) in every representation.

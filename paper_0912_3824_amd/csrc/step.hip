@@ -119,6 +119,9 @@ __device__ __forceinline__ uint4 snap_of(const StateD &s, const RepDev &r, uint3
 // r2s = r^2 / u^2 the pair term needs rc^2/u^2, sigma^2/u^2 and 24 eps / u.
 struct LaneConsts {
     float rc2s[2], sig2s[2], e24s[2];
+    // smoothing (Sec. 4): rc in fixed-point units, u/(h sigma), 1/(h sigma),
+    // 4 eps and the energy shift
+    float rcs[2], xsc[2], ihs[2], e4[2], sh[2];
 };
 
 __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, const RepDev &r)
@@ -132,9 +135,19 @@ __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, con
         c.rc2s[b] = (float)(pp.rc2d[t] * iu2);
         c.sig2s[b] = (float)(pp.sig2d[t] * iu2);
         c.e24s[b] = (float)(pp.eps24d[t] / u);
+        c.rcs[b] = (float)(pp.rcd[t] / u);
+        c.xsc[b] = pp.smooth ? (float)(u / pp.hsd[t]) : 0.0f;
+        c.ihs[b] = pp.smooth ? (float)(1.0 / pp.hsd[t]) : 0.0f;
+        c.e4[b] = pp.eps4[t];
+        c.sh[b] = pp.shift[t];
     }
     return c;
 }
+
+// Pair kinds of the force loop: plain truncation with a cutoff per species
+// pair, plain truncation with one cutoff ratio rc_ab / sigma_ab for every
+// pair (the test needs no per-pair cutoff), and the C2-smoothed potential.
+enum { PK_GENERAL = 0, PK_UNIFORM = 1, PK_SMOOTH = 2 };
 
 // The Verlet list of particle i is stored in blocks of four entries:
 // entry k lives in int4 row k/4, lane k%4, of column i (nbr4[(k/4)*P + i]),
@@ -149,8 +162,12 @@ __device__ __forceinline__ int4 list_row(const KArena &A, int i, int q)
 
 // One list entry, fixed-point snapshots, FP32 pair term.  With a uniform
 // cutoff ratio (rc_ab = c sigma_ab for every pair) the cutoff test is
-// sigma^2/r^2 > 1/c^2 and needs no per-pair cutoff.
-template <int P, bool EN, bool UNI>
+// sigma^2/r^2 > 1/c^2 and needs no per-pair cutoff.  Smoothed (Sec. 4):
+// V_s = V_ts g(x), x = (r - rc)/(h sigma), g = x^4/(1+x^4), and
+// -dV_s/dr = F g - V_ts g'(x)/(h sigma), g' = 4x^3/(1+x^4)^2.  In fixed-
+// point units r' = r/u, so x = (r' - rc/u) u/(h sigma) and the force factor
+// per unit of separation gains -V_ts g' / (h sigma r').
+template <int P, bool EN, int KIND>
 __device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts &c, const PairDev &pp,
                                             int si, FAcc<P> &acc, double &e_sum, double &w_sum)
 {
@@ -166,15 +183,33 @@ __device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts
     const float t = __builtin_fmaf(2.0f, s6, -1.0f);
     float fs = e24 * ir2 * s6 * t;
     bool in;
-    if (UNI) in = s2 > pp.s2cut;
+    if (KIND == PK_UNIFORM) in = s2 > pp.s2cut;
     else in = r2 < (b ? c.rc2s[1] : c.rc2s[0]);
+    float g = 1.0f, vts = 0.0f, dgr = 0.0f;
+    if (KIND == PK_SMOOTH) {
+        const float irr = __builtin_amdgcn_rsqf(r2); // 1 / r'
+        const float rr = r2 * irr;
+        const float x = (rr - (b ? c.rcs[1] : c.rcs[0])) * (b ? c.xsc[1] : c.xsc[0]);
+        const float x2 = x * x, x4 = x2 * x2;
+        const float iden = __builtin_amdgcn_rcpf(1.0f + x4);
+        g = x4 * iden;
+        const float dg = 4.0f * x2 * x * iden * iden;
+        vts = (b ? c.e4[1] : c.e4[0]) * s6 * (s6 - 1.0f) - (b ? c.sh[1] : c.sh[0]);
+        dgr = dg * rr * (b ? c.xsc[1] : c.xsc[0]); // r g'(x) / (h sigma)
+        fs = fs * g - vts * dg * (b ? c.ihs[1] : c.ihs[0]) * irr;
+    }
     fs = in ? fs : 0.0f;
     acc.add(fs, dx, dy, dz, ix, iy, iz);
     if (EN) {
         const int tt = si * 2 + (b ? 1 : 0);
         if (in) {
-            e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
-            w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
+            if (KIND == PK_SMOOTH) {
+                e_sum += 0.5 * (double)(vts * g);
+                w_sum += 0.5 * (double)(g * pp.eps24[tt] * s6 * t - vts * dgr);
+            } else {
+                e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
+                w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
+            }
         }
     }
 }
@@ -192,7 +227,7 @@ __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int j)
 // multiple of eight valid entries by the list build and row indices are clamped, so every
 // prefetch is unconditional and no control-flow join forces the memory
 // counters to drain inside the loop.
-template <int P, bool EN, bool UNI>
+template <int P, bool EN, int KIND>
 __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
                                             uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
                                             FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp)
@@ -216,10 +251,10 @@ __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__rest
                     b3 = ld_snap(snap, jb.w);
         jb = list_row(A, i, min(2 * (p + lpp) + 1, last));
         __builtin_amdgcn_sched_barrier(0);
-        entry_fixed<P, EN, UNI>(xi, a0, c, pp, si, acc, e_sum, w_sum);
-        entry_fixed<P, EN, UNI>(xi, a1, c, pp, si, acc, e_sum, w_sum);
-        entry_fixed<P, EN, UNI>(xi, a2, c, pp, si, acc, e_sum, w_sum);
-        entry_fixed<P, EN, UNI>(xi, a3, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a3, c, pp, si, acc, e_sum, w_sum);
         __builtin_amdgcn_sched_barrier(0);
         a0 = ld_snap(snap, ja.x);
         a1 = ld_snap(snap, ja.y);
@@ -227,15 +262,17 @@ __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__rest
         a3 = ld_snap(snap, ja.w);
         ja = list_row(A, i, min(2 * (p + 2 * lpp), last));
         __builtin_amdgcn_sched_barrier(0);
-        entry_fixed<P, EN, UNI>(xi, b0, c, pp, si, acc, e_sum, w_sum);
-        entry_fixed<P, EN, UNI>(xi, b1, c, pp, si, acc, e_sum, w_sum);
-        entry_fixed<P, EN, UNI>(xi, b2, c, pp, si, acc, e_sum, w_sum);
-        entry_fixed<P, EN, UNI>(xi, b3, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, b0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, b1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, b2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, b3, c, pp, si, acc, e_sum, w_sum);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// FP64 path: double snapshots, textbook minimum image, FP64 pair term.
+// FP64 path: double snapshots, textbook minimum image, FP64 pair term
+// (smoothed as in entry_fixed when SMOOTH).
+template <bool SMOOTH>
 __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restrict__ snap, int i,
                                           double xi, double yi, double zi, int si, const RepDev &r,
                                           const PairDev &pp, double &fx, double &fy, double &fz,
@@ -270,13 +307,26 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
             double s6 = s2 * s2 * s2;
             double ff = e24[b] * ir2 * s6 * (2.0 * s6 - 1.0);
             bool in = r2 < rc2[b];
+            double vs = 0.0;
+            if (en || SMOOTH) {
+                const int tt = si * 2 + b;
+                vs = pp.eps4d[tt] * s6 * (s6 - 1.0) - pp.shiftd[tt];
+                if (SMOOTH) {
+                    const double r = sqrt(r2);
+                    const double x = (r - pp.rcd[tt]) / pp.hsd[tt];
+                    const double x2 = x * x, x4 = x2 * x2;
+                    const double g = x4 / (1.0 + x4);
+                    const double dg = 4.0 * x2 * x / ((1.0 + x4) * (1.0 + x4));
+                    ff = ff * g - vs * dg / pp.hsd[tt] / r;
+                    vs *= g;
+                }
+            }
             ff = in ? ff : 0.0;
             fx += ff * dx;
             fy += ff * dy;
             fz += ff * dz;
             if (en && in) {
-                int tt = si * 2 + b;
-                e_sum += 0.5 * (pp.eps4d[tt] * s6 * (s6 - 1.0) - pp.shiftd[tt]);
+                e_sum += 0.5 * vs;
                 w_sum += 0.5 * ff * r2;
             }
         }
@@ -286,7 +336,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
 // ------------------------------------------------------------ k_step
 enum { M_ADV = 0, M_FIN = 1, M_IDLE = 2 };
 
-template <int P, bool OBS, bool UNI, int LPP>
+template <int P, bool OBS, int KIND, int LPP>
 __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
 {
     const KArena &A = a.A;
@@ -354,7 +404,8 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         double xi, yi, zi, wi;
         u4_to_dbl2(s0, xi, yi);
         u4_to_dbl2(s1, zi, wi);
-        force_dbl(A, a.snap_cur, i, xi, yi, zi, si, rp, a.pp, fxd, fyd, fzd, OBS, e_sum, w_sum, sub, LPP);
+        force_dbl<KIND == PK_SMOOTH>(A, a.snap_cur, i, xi, yi, zi, si, rp, a.pp, fxd, fyd, fzd, OBS, e_sum,
+                                     w_sum, sub, LPP);
 #pragma unroll
         for (int m = 1; m < LPP; m <<= 1) {
             lane_sum(fxd, m); lane_sum(fyd, m); lane_sum(fzd, m);
@@ -375,7 +426,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     } else {
         const LaneConsts c = lane_consts(a.pp, si, rp);
         FAcc<P> acc;
-        force_fixed<P, OBS, UNI>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum, sub, LPP);
+        force_fixed<P, OBS, KIND>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum, sub, LPP);
         // combine the lanes' partial sums (a no-op for one lane per particle)
         DsForce F;
         if constexpr (P == PREC_DS) F = {acc.x.result(), acc.y.result(), acc.z.result()};
@@ -461,11 +512,20 @@ static hipError_t launch_step_l(const StepArgs &a, int block, bool obs, hipStrea
 {
     const long long threads = (long long)a.A.P * LPP;
     const int grid = (int)((threads + block - 1) / block);
-    const bool uni = a.pp.uniform != 0 && P != PREC_FP64;
-    if (obs && uni) hipLaunchKernelGGL((k_step<P, true, true, LPP>), dim3(grid), dim3(block), 0, s, a);
-    else if (obs) hipLaunchKernelGGL((k_step<P, true, false, LPP>), dim3(grid), dim3(block), 0, s, a);
-    else if (uni) hipLaunchKernelGGL((k_step<P, false, true, LPP>), dim3(grid), dim3(block), 0, s, a);
-    else hipLaunchKernelGGL((k_step<P, false, false, LPP>), dim3(grid), dim3(block), 0, s, a);
+    if (a.pp.smooth) {
+        if (obs) hipLaunchKernelGGL((k_step<P, true, PK_SMOOTH, LPP>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_step<P, false, PK_SMOOTH, LPP>), dim3(grid), dim3(block), 0, s, a);
+        LAUNCH_CHECK();
+    }
+    if constexpr (P != PREC_FP64) {
+        if (a.pp.uniform) {
+            if (obs) hipLaunchKernelGGL((k_step<P, true, PK_UNIFORM, LPP>), dim3(grid), dim3(block), 0, s, a);
+            else hipLaunchKernelGGL((k_step<P, false, PK_UNIFORM, LPP>), dim3(grid), dim3(block), 0, s, a);
+            LAUNCH_CHECK();
+        }
+    }
+    if (obs) hipLaunchKernelGGL((k_step<P, true, PK_GENERAL, LPP>), dim3(grid), dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, false, PK_GENERAL, LPP>), dim3(grid), dim3(block), 0, s, a);
     LAUNCH_CHECK();
 }
 

@@ -45,7 +45,7 @@ class MdConfig(ctypes.Structure):
                 ("nbr_capacity", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("max_particles", ctypes.c_int64), ("max_cells", ctypes.c_int64),
                 ("max_density", ctypes.c_double), ("lanes_per_particle", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("smooth", ctypes.c_double)]
 
 
 class MdReplica(ctypes.Structure):
@@ -154,7 +154,8 @@ def make_config(table, precision, dt: float, skin: float, max_slots: int,
                 max_particles: int, mass: float = 1.0, nbr_capacity: int = 0,
                 max_cells: int = 0, max_density: float = 0.0,
                 lanes_per_particle: int = 0) -> MdConfig:
-    """md_config from a pair table (md_inputs.PairTable) and run parameters."""
+    """md_config from a pair table (md_inputs.PairTable, including its
+    smoothing width) and run parameters."""
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     c = MdConfig()
@@ -172,6 +173,7 @@ def make_config(table, precision, dt: float, skin: float, max_slots: int,
     c.max_cells = int(max_cells)
     c.max_density = float(max_density)
     c.lanes_per_particle = int(lanes_per_particle)
+    c.smooth = float(getattr(table, "smooth", 0.0))
     return c
 
 

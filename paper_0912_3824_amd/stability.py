@@ -1,0 +1,161 @@
+"""Numerical long-time stability of the MD step (Sec. 4 of the paper) on the
+GPU path: LJ and WCA fluids with and without the C2 smoothing factor
+g(x) = x^4 / (1 + x^4), in single, double-single and double precision.
+
+  collapse: [E(t) - E(0)] / dt^2 over 200..1000 steps for dt = 0.001..0.005
+            (Sec. 4.3); velocity Verlet's error is second order only for a
+            potential with a continuous second derivative, so the curves for
+            different dt coincide ("collapse") when the arithmetic is precise
+            enough and the potential is smooth.  Reported: the spread of the
+            curves, sqrt(mean_t var_dt q) / sqrt(mean_t mean_dt q^2).
+  drift:    OLS slope of E_tot/N per 1e5 steps (Sec. 4.2) and the largest
+            centre-of-mass speed |sum v|/N reached (Sec. 4.1).
+  speed:    particle-steps/s of WCA against LJ (Sec. 4: shorter lists).
+
+All runs of one potential start from the same state: an fcc lattice
+equilibrated by velocity rescaling in double precision with h = 0.005 (the
+paper equilibrates with an Andersen thermostat; the thermostat is not part
+of this build).  System: N = 10,000, rho = 0.75, T = 1.12, as in Sec. 4.
+
+  python -m paper_0912_3824_amd.stability [--steps 200000] [--n 10000]
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print("[stability]", *a, file=sys.stderr, flush=True)
+
+
+def equilibrated(n: int, rc: float, rho: float, temperature: float, steps: int, seed: int):
+    """Lattice start equilibrated by velocity rescaling (FP64, h = 0.005)."""
+    import md_inputs as I
+    from paper_0912_3824_amd import mdx
+    s = I.smoothed(I.make_lj(n, rho=rho, temperature=temperature, seed=seed, jitter=0.05, rc=rc), 0.005)
+    s = dataclasses.replace(s, dt=0.002)
+    pool = mdx.md_init([s], "fp64")
+    done = 0
+    while done < steps:
+        pool.step(100)
+        done += 100
+        o = pool.observables()[0]
+        pool.scale_velocities(0, math.sqrt(temperature / o["temperature"]))
+    pos, vel, _ = pool.get_state(0)
+    pool.close()
+    return dataclasses.replace(s, pos=pos, vel=vel)
+
+
+def _energy_series(s, prec: str, h: float, dt: float, steps: int, every: int):
+    import md_inputs as I
+    from paper_0912_3824_amd import mdx
+    r = dataclasses.replace(I.smoothed(s, h), dt=dt)
+    pool = mdx.md_init([r], prec)
+    o = pool.observables()[0]
+    t, e, p = [0], [o["etot"] / r.n], [float(np.abs(o["momentum"]).max()) / r.n]
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        pool.step(k)
+        done += k
+        o = pool.observables()[0]
+        if o["status"]:
+            raise RuntimeError(f"replica status {o['status']}")
+        t.append(done)
+        e.append(o["etot"] / r.n)
+        p.append(float(np.abs(o["momentum"]).max()) / r.n)
+    pool.close()
+    return np.array(t), np.array(e), np.array(p)
+
+
+def collapse(s, precs, hs, dts=(0.001, 0.002, 0.003, 0.004, 0.005), steps=1000, every=10,
+             window=(200, 1000)) -> dict:
+    out = {}
+    for prec in precs:
+        for h in hs:
+            qs = []
+            for dt in dts:
+                t, e, _ = _energy_series(s, prec, h, dt, steps, every)
+                qs.append((e - e[0]) / dt ** 2)
+            q = np.array(qs)
+            sel = (t >= window[0]) & (t <= window[1])
+            qw = q[:, sel]
+            spread = float(np.sqrt(np.mean(np.var(qw, axis=0))) / np.sqrt(np.mean(np.mean(qw, axis=0) ** 2)))
+            key = f"{prec}_h{h}"
+            out[key] = {"spread": spread, "q_rms_per_dt": [float(np.sqrt(np.mean(x ** 2))) for x in qw]}
+            log(f"collapse {key}: spread {spread:.3g}")
+    return out
+
+
+def drift(s, precs, hs, dts, steps, every) -> dict:
+    from paper_0912_3824_amd.drift import slope_with_error
+    out = {}
+    for prec in precs:
+        for h in hs:
+            for dt in dts:
+                t0 = time.perf_counter()
+                t, e, p = _energy_series(s, prec, h, dt, steps, every)
+                b, se, g = slope_with_error(t, e)
+                key = f"{prec}_h{h}_dt{dt}"
+                out[key] = {"slope_per_1e5_steps": b * 1e5, "stderr_per_1e5_steps": se * 1e5,
+                            "relative_slope_per_1e5_steps": b * 1e5 / abs(e[0]),
+                            "rms_dev_from_e0": float(np.sqrt(np.mean((e - e[0]) ** 2))),
+                            "max_cm_speed_per_particle": float(p.max()),
+                            "wall_s": time.perf_counter() - t0}
+                log(f"drift {key}: {json.dumps(out[key])}")
+    return out
+
+
+def speed(s, prec="ds", steps=2000) -> dict:
+    import torch
+    from paper_0912_3824_amd import mdx
+    pool = mdx.md_init([s], prec)
+    pool.step(200)
+    pool.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pool.step(steps)
+    pool.sync()
+    dt = time.perf_counter() - t0
+    o = pool.observables()[0]
+    pool.close()
+    return {"particle_steps_per_s": s.n * steps / dt, "us_per_step": dt / steps * 1e6,
+            "mean_list_entries": o["list_entries"] / s.n}
+
+
+def run(n=10000, rho=0.75, temperature=1.12, equil=20000, drift_steps=200000, seed=20240101) -> dict:
+    import md_inputs as I
+    res = {"n": n, "rho": rho, "temperature": temperature, "equil_steps": equil}
+    states = {}
+    for name, rc in (("lj", 2.5), ("wca", I.WCA_RC)):
+        t0 = time.perf_counter()
+        states[name] = equilibrated(n, rc, rho, temperature, equil, seed)
+        log(f"equilibrated {name} in {time.perf_counter() - t0:.1f} s")
+    res["collapse_lj"] = collapse(states["lj"], ("fp32", "ds", "fp64"), (0.0, 0.01))
+    res["drift"] = {}
+    for name in ("lj", "wca"):
+        res["drift"][name] = drift(states[name], ("fp32", "ds", "fp64"), (0.0, 0.005), (0.001, 0.003),
+                                   drift_steps, max(100, drift_steps // 500))
+    res["speed"] = {name: speed(states[name]) for name in ("lj", "wca")}
+    log(f"speed {json.dumps(res['speed'])}")
+    return res
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--equil", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=200000, help="steps per drift run")
+    a = ap.parse_args()
+    print(json.dumps(run(n=a.n, equil=a.equil, drift_steps=a.steps)))

@@ -293,6 +293,44 @@ md_status md_get_launch(const md_system *sys, md_launch *out);
 /* Changes take effect for later launches; captured graphs are dropped. */
 md_status md_set_launch(md_system *sys, const md_launch *in);
 
+/* ---- time-correlation functions (Sec. 2.5, blocking scheme) -------------------- */
+
+typedef struct md_tcf md_tcf;
+
+/* Bytes of device workspace of a blocking scheme of `levels` blocks of
+ * `block` entries for a replica of n particles, or MD_E_ARG (levels in
+ * [1, 16], block in [2, 33]).  Host only. */
+int64_t md_tcf_workspace_bytes(int32_t n, int32_t levels, int32_t block);
+
+/* Bind a blocking scheme (Sec. 2.5) to the replica attached at `slot`:
+ * samples fill `levels` blocks of `block` entries, block n holding every
+ * block^n-th sample; a full block correlates its oldest entry with the
+ * others (time lags j block^n samples, j = 1 .. block-1) and drops it.  Per
+ * species it accumulates the tagged-particle means of the mean-square
+ * displacement (unwrapped positions), the velocity autocorrelation and the
+ * self-intermediate scattering function F_s(q, t) = <cos(q dx)>, averaged
+ * over the three box axes at wave number q (> 0).  The workspace (device,
+ * 256-byte aligned, md_tcf_workspace_bytes) is caller-owned and must stay
+ * valid until md_tcf_destroy; the replica must stay attached.  Errors:
+ * MD_E_NOSLOT, MD_E_ARG, MD_E_WORKSPACE, MD_E_HIP. */
+md_status md_tcf_create(md_system *sys, int32_t slot, int32_t levels, int32_t block, double q,
+                        void *workspace, int64_t ws_bytes, md_tcf **out);
+
+/* Record the replica's current state as the next sample.  The replica must
+ * be at a full step (as after md_step, or once md_advance reached its
+ * target).  Asynchronous on the pool's stream. */
+md_status md_tcf_sample(md_tcf *tcf);
+
+/* Synchronise and read, for k = level * (block - 1) + (j - 1):
+ * lags[k] = j block^level (in samples), terms[k] = correlation passes so
+ * far, values[6k .. 6k+5] = (MSD, VACF, F_s) of species A then B, each the
+ * mean over passes of the species mean (NaN before the first pass).  Any
+ * output may be NULL. */
+md_status md_tcf_read(md_tcf *tcf, int64_t *lags, double *values, int64_t *terms);
+
+/* Release the host handle (the workspace belongs to the caller). */
+void md_tcf_destroy(md_tcf *tcf);
+
 /* ---- double-single arithmetic self-test (Sec. 2.4, Alg. 1) -------------------- */
 
 /* Element-wise double-single operation on device arrays of n (hi, lo) float

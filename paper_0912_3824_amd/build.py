@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdx.so")
-SOURCES = ["step.hip", "rebuild.hip", "aux_kernels.hip", "abi.cpp"]
+SOURCES = ["step.hip", "rebuild.hip", "aux_kernels.hip", "tcf.hip", "abi.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no silent contraction of a*b+c: the double-single code relies on

@@ -18,6 +18,7 @@
 #include "../../include/md.h"
 #include "kernels.hpp"
 #include "md_dev.hpp"
+#include "tcf.hpp"
 
 namespace {
 
@@ -1515,6 +1516,152 @@ md_status md_set_launch(md_system *s, const md_launch *in)
         }
     return upload_items(s);
 }
+
+// ------------------------------------------------- time-correlation functions
+struct md_tcf {
+    md_system *s = nullptr;
+    int slot = 0, n = 0, levels = 0, block = 0;
+    double q = 0, L = 0;
+    int64_t samples = 0;
+    std::vector<int64_t> inserted; // entries inserted per level
+    std::vector<int64_t> terms;    // correlation passes per level (every lag alike)
+    double4 *pos = nullptr;
+    double4 *vel = nullptr;
+    int *species = nullptr;
+    double *partial = nullptr, *acc = nullptr;
+};
+
+namespace {
+struct TcfLayout {
+    int64_t pos, vel, species, partial, acc, total;
+};
+
+TcfLayout tcf_layout(int64_t n, int levels, int block)
+{
+    TcfLayout t;
+    int64_t off = 0;
+    const int64_t entries = (int64_t)levels * block;
+    t.pos = off; off = align_up(off + entries * n * 32, ALIGN);
+    t.vel = off; off = align_up(off + entries * n * 32, ALIGN);
+    t.species = off; off = align_up(off + n * 4, ALIGN);
+    t.partial = off; off = align_up(off + (int64_t)tcf_blocks((int)n) * (block - 1) * 8 * 8, ALIGN);
+    t.acc = off; off = align_up(off + (int64_t)levels * (block - 1) * 6 * 8, ALIGN);
+    t.total = off;
+    return t;
+}
+
+bool tcf_shape_ok(int64_t n, int levels, int block)
+{
+    return n >= 1 && n <= ((int64_t)1 << 30) && levels >= 1 && levels <= 16 && block >= 2 && block <= 33;
+}
+} // namespace
+
+int64_t md_tcf_workspace_bytes(int32_t n, int32_t levels, int32_t block)
+{
+    if (!tcf_shape_ok(n, levels, block)) return MD_E_ARG;
+    return tcf_layout(n, levels, block).total;
+}
+
+md_status md_tcf_create(md_system *s, int32_t slot, int32_t levels, int32_t block, double q, void *workspace,
+                        int64_t ws_bytes, md_tcf **out)
+{
+    if (!s || !out) return MD_E_ARG;
+    *out = nullptr;
+    if (slot < 0 || slot >= (int)s->lay.slots || !s->slots[slot].attached)
+        return fail(s, MD_E_NOSLOT, "slot %d is not attached", slot);
+    const SlotHost &h = s->slots[slot];
+    if (!tcf_shape_ok(h.n, levels, block)) return fail(s, MD_E_ARG, "levels in [1, 16], block in [2, 33]");
+    if (!(q > 0) || !std::isfinite(q)) return fail(s, MD_E_ARG, "q must be positive and finite");
+    const TcfLayout t = tcf_layout(h.n, levels, block);
+    if (!workspace || ws_bytes < t.total || ((uintptr_t)workspace % ALIGN) != 0)
+        return fail(s, MD_E_WORKSPACE, "time-correlation workspace missing, misaligned or smaller than %lld bytes",
+                    (long long)t.total);
+    md_tcf *c = new md_tcf();
+    c->s = s;
+    c->slot = slot;
+    c->n = h.n;
+    c->levels = levels;
+    c->block = block;
+    c->q = q;
+    c->L = h.L;
+    c->inserted.assign(levels, 0);
+    c->terms.assign(levels, 0);
+    char *w = (char *)workspace;
+    c->pos = (double4 *)(w + t.pos);
+    c->vel = (double4 *)(w + t.vel);
+    c->species = (int *)(w + t.species);
+    c->partial = (double *)(w + t.partial);
+    c->acc = (double *)(w + t.acc);
+    if (hipMemsetAsync(c->acc, 0, (size_t)levels * (block - 1) * 6 * 8, s->stream) != hipSuccess) {
+        delete c;
+        return fail(s, MD_E_HIP, "hipMemsetAsync failed");
+    }
+    *out = c;
+    return MD_OK;
+}
+
+md_status md_tcf_sample(md_tcf *c)
+{
+    if (!c) return MD_E_ARG;
+    md_system *s = c->s;
+    const SlotHost &h = s->slots[c->slot];
+    if (!h.attached || h.n != c->n) return fail(s, MD_E_STATE, "the replica of this scheme was detached");
+    TcfArgs a;
+    memset(&a, 0, sizeof a);
+    a.A = arena_of(s);
+    a.snap = s->snap[s->parity];
+    a.off = (int)h.off;
+    a.n = c->n;
+    a.block = c->block;
+    a.L = c->L;
+    a.q = c->q;
+    a.pos = c->pos;
+    a.vel = c->vel;
+    a.species = c->species;
+    a.partial = c->partial;
+    a.acc = c->acc;
+    int64_t stride = 1; // block^level, the level's resolution in samples
+    for (int lev = 0; lev < c->levels; ++lev) {
+        if (c->samples % stride) break;
+        const int r = (int)(c->inserted[lev] % c->block);
+        HIPCHK(s, launch_tcf_store(s->prec, a, lev * c->block + r, s->stream));
+        c->inserted[lev] += 1;
+        if (c->inserted[lev] >= c->block) { // full: oldest entry against the others, then dropped
+            const int head = (int)((c->inserted[lev] - c->block) % c->block);
+            HIPCHK(s, launch_tcf_correlate(a, lev, head, s->stream));
+            c->terms[lev] += 1;
+        }
+        if (stride > ((int64_t)1 << 40) / c->block) break;
+        stride *= c->block;
+    }
+    c->samples += 1;
+    return MD_OK;
+}
+
+md_status md_tcf_read(md_tcf *c, int64_t *lags, double *values, int64_t *terms)
+{
+    if (!c) return MD_E_ARG;
+    md_system *s = c->s;
+    const int nl = c->block - 1;
+    std::vector<double> acc((size_t)c->levels * nl * 6);
+    HIPCHK(s, hipMemcpyAsync(acc.data(), c->acc, acc.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    int64_t stride = 1;
+    for (int lev = 0; lev < c->levels; ++lev) {
+        for (int j = 1; j <= nl; ++j) {
+            const size_t k = (size_t)lev * nl + (j - 1);
+            if (lags) lags[k] = j * stride;
+            if (terms) terms[k] = c->terms[lev];
+            if (values)
+                for (int q = 0; q < 6; ++q)
+                    values[k * 6 + q] = c->terms[lev] ? acc[k * 6 + q] / (double)c->terms[lev] : NAN;
+        }
+        stride = stride > ((int64_t)1 << 40) / c->block ? stride : stride * c->block;
+    }
+    return MD_OK;
+}
+
+void md_tcf_destroy(md_tcf *c) { delete c; }
 
 md_status md_ds_eval(int32_t op, int64_t n, const float *a, const float *b, float *out, void *hip_stream)
 {

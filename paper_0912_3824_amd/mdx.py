@@ -33,7 +33,8 @@ EXPORTS = [
     "md_scale_velocities", "md_profile_steps", "md_sync", "md_get_state", "md_checkpoint_bytes",
     "md_save", "md_restore", "md_debug_neighbours", "md_get_launch",
     "md_set_launch", "md_ds_eval", "md_strerror", "md_last_error",
-    "md_abi_version",
+    "md_abi_version", "md_tcf_workspace_bytes", "md_tcf_create", "md_tcf_sample",
+    "md_tcf_read", "md_tcf_destroy",
 ]
 
 
@@ -133,6 +134,11 @@ def load():
         "md_strerror": (ctypes.c_char_p, [i32]),
         "md_last_error": (ctypes.c_char_p, [vp]),
         "md_abi_version": (i32, []),
+        "md_tcf_workspace_bytes": (i64, [i32, i32, i32]),
+        "md_tcf_create": (i32, [vp, i32, i32, i32, ctypes.c_double, vp, i64, ctypes.POINTER(vp)]),
+        "md_tcf_sample": (i32, [vp]),
+        "md_tcf_read": (i32, [vp, i64p, dp, i64p]),
+        "md_tcf_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -202,6 +208,46 @@ def md_ds_eval(op: int, a, b, out, stream=None) -> None:
         raise MdError(st, "md_ds_eval")
 
 
+class Tcf:
+    """Time-correlation functions of one replica by the blocking scheme
+    (md_tcf_*): sample() after each sampling interval; read() returns the
+    lags (in samples), term counts and per-species (MSD, VACF, F_s) means."""
+
+    def __init__(self, pool: "MdSystem", slot: int, levels: int, block: int, q: float):
+        import torch
+        self.pool, self.lib = pool, pool.lib
+        self.levels, self.block = int(levels), int(block)
+        n = pool.sizes[slot]
+        nbytes = int(self.lib.md_tcf_workspace_bytes(n, self.levels, self.block))
+        if nbytes < 0:
+            raise MdError(nbytes, "md_tcf_workspace_bytes")
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=pool.device)
+        h = ctypes.c_void_p()
+        pool._check(self.lib.md_tcf_create(pool.h, int(slot), self.levels, self.block, float(q),
+                                           ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_int64(nbytes),
+                                           ctypes.byref(h)), "md_tcf_create")
+        self.h = h
+
+    def sample(self):
+        self.pool._check(self.lib.md_tcf_sample(self.h), "md_tcf_sample")
+
+    def read(self):
+        k = self.levels * (self.block - 1)
+        lags = np.zeros(k, dtype=np.int64)
+        terms = np.zeros(k, dtype=np.int64)
+        vals = np.zeros(k * 6)
+        self.pool._check(self.lib.md_tcf_read(self.h, lags.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              _dp(vals), terms.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                         "md_tcf_read")
+        return (lags.reshape(self.levels, self.block - 1), vals.reshape(self.levels, self.block - 1, 2, 3),
+                terms.reshape(self.levels, self.block - 1))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.md_tcf_destroy(self.h)
+            self.h = None
+
+
 class MdSystem:
     """A pool of replica slots on one GPU (md_create / md_init and friends).
 
@@ -239,9 +285,18 @@ class MdSystem:
             raise MdError(st, f"{what}: {txt.decode() if txt else ''}")
 
     def close(self):
+        for t in list(getattr(self, "_tcfs", [])):
+            t.close()
         if getattr(self, "h", None):
             self.lib.md_destroy(self.h)
             self.h = None
+
+    def tcf(self, slot: int, levels: int, block: int, q: float) -> "Tcf":
+        """A blocking scheme for time-correlation functions bound to `slot`
+        (md_tcf_create); see Tcf."""
+        t = Tcf(self, slot, levels, block, q)
+        self.__dict__.setdefault("_tcfs", []).append(t)
+        return t
 
     def __del__(self):
         try:

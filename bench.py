@@ -154,7 +154,10 @@ def main():
     log(f"workload {args.workload}: {len(systems)} replica(s), {n_total} particles, precision {prec}")
 
     pool = mdx.md_init(systems, prec)
+    from paper_0912_3824_amd import tune
+    tuned = tune.apply_cached(pool)  # launch shapes from the autotuner, if tuned
     pool.set_launch(graph_steps=args.graph_steps)
+    log(f"launch shapes: {pool.get_launch()} ({'autotuned' if tuned else 'defaults'})")
     if args.equil > 0:
         equilibrate(pool, systems, args.equil)
     pool.step(args.warmup)
@@ -240,6 +243,7 @@ def main():
         "config": {"workload": args.workload, "description": desc, "particles": n_total,
                    "replicas": len(systems), "precision": prec, "skin": systems[0].skin,
                    "graph_steps": args.graph_steps, "equil_steps": args.equil,
+                   "launch": pool.get_launch(),
                    "mean_list_entries": round(mean_list, 3), "rebuilds_in_timed_region": int(rebuilds)},
         "breakdown": {"step_kernel_ms": round(k_ms, 5),
                       "rebuild_group_ms_mean": round(prof["rebuild_ms_mean"], 5),

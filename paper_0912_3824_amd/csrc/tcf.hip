@@ -126,20 +126,32 @@ __global__ void __launch_bounds__(TCF_BLOCK) k_tcf_corr(const TcfArgs a, int lev
     }
 }
 
-// Add the partial rows of one pass in block order; accumulate per-pass
-// species means into acc[level][j][species][3].
-__global__ void k_tcf_reduce(const TcfArgs a, int level, int nblk)
+// Add the partial rows of one pass (one workgroup per lag and species: each
+// thread sums a fixed stride of rows, then a fixed tree), and accumulate the
+// per-pass species means into acc[level][j][species][3].
+__global__ void __launch_bounds__(TCF_BLOCK) k_tcf_reduce(const TcfArgs a, int level, int nblk)
 {
-    const int t = threadIdx.x; // t = (j - 1) * 2 + species
+    __shared__ double red[4][TCF_BLOCK];
+    const int t = threadIdx.x;
     const int l = a.block;
-    if (t >= 2 * (l - 1)) return;
-    const int j = t >> 1, s = t & 1;
+    const int j = blockIdx.x >> 1, s = blockIdx.x & 1;
     double sum[4] = {0, 0, 0, 0};
-    for (int b = 0; b < nblk; ++b)
+    for (int b = t; b < nblk; b += TCF_BLOCK)
+#pragma unroll
         for (int c = 0; c < 4; ++c) sum[c] += a.partial[((size_t)b * (l - 1) + j) * 8 + s * 4 + c];
-    double *acc = a.acc + (((size_t)level * (l - 1) + j) * 2 + s) * 3;
-    if (sum[3] > 0)
-        for (int c = 0; c < 3; ++c) acc[c] += sum[c] / sum[3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][t] = sum[c];
+    __syncthreads();
+    for (int w = TCF_BLOCK >> 1; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][t] += red[c][t + w];
+        __syncthreads();
+    }
+    if (t == 0 && red[3][0] > 0) {
+        double *acc = a.acc + (((size_t)level * (l - 1) + j) * 2 + s) * 3;
+        for (int c = 0; c < 3; ++c) acc[c] += red[c][0] / red[3][0];
+    }
 }
 
 hipError_t launch_tcf_store(int prec, const TcfArgs &a, int entry, hipStream_t s)
@@ -160,6 +172,6 @@ hipError_t launch_tcf_correlate(const TcfArgs &a, int level, int head, hipStream
 {
     const int grid = tcf_blocks(a.n);
     hipLaunchKernelGGL(k_tcf_corr, dim3(grid), dim3(TCF_BLOCK), 0, s, a, level, head);
-    hipLaunchKernelGGL(k_tcf_reduce, dim3(1), dim3(64), 0, s, a, level, grid);
+    hipLaunchKernelGGL(k_tcf_reduce, dim3(2 * (a.block - 1)), dim3(TCF_BLOCK), 0, s, a, level, grid);
     LAUNCH_CHECK();
 }

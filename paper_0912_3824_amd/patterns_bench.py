@@ -4,11 +4,15 @@ results).
 
   python -m paper_0912_3824_amd.patterns_bench batch [--replicas 256 --steps 2000]
   python -m paper_0912_3824_amd.patterns_bench serve [--jobs 40 --load 0.8]
+  python -m paper_0912_3824_amd.patterns_bench tcf   [--steps 3000]
 
 batch: 256 Kob-Andersen replicas, N log-uniform in [500, 8000], rho = 1.2,
        T from {0.45, 0.5, 0.6, 0.8}, advanced together in one pool (one
        fused launch per step for all replicas, graph-captured); compared with
        a sample of the same replicas advanced one at a time.
+tcf:   the N = 1M KA run with on-device time-correlation functions
+       (blocking scheme, Sec. 2.5) sampled every 10 steps, against the same
+       run without them.
 serve: Poisson arrivals of KA jobs, N log-uniform in [1000, 256000], steps
        uniform in [steps_lo, steps_hi], T uniform in [0.45, 1.0]; admission
        by arena footprint; p50/p99 latency and throughput over the busy
@@ -116,9 +120,57 @@ def serve(n_jobs=40, load=0.8, steps_lo=1000, steps_hi=10000, n_lo=1000, n_hi=25
     return res
 
 
+def tcf(n=1_000_000, steps=3000, every=10, levels=4, block=10, precision="ds", seed=20240101):
+    """Cost of on-device time-correlation functions (blocking scheme) at the
+    N = 1M KA workload: the same run with and without a sample every `every`
+    steps, and the MSD / F_s / VACF the scheme produces."""
+    import torch
+    import md_inputs as I
+    from paper_0912_3824_amd import mdx
+    s = I.make_ka(n, 0.5, seed=seed)
+    pool = mdx.md_init([s], precision)
+    for _ in range(10):
+        pool.step(100)
+        o = pool.observables()[0]
+        pool.scale_velocities(0, math.sqrt(0.5 / o["temperature"]))
+    blob = pool.save(0)
+
+    def chunks(sample):  # the same launch pattern with and without sampling
+        pool.step(200)
+        pool.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            if sample:
+                sample()
+            pool.step(every)
+            done += every
+        pool.sync()
+        return time.perf_counter() - t0
+
+    base = chunks(None)
+    pool.detach(0)
+    pool.restore(0, blob, s.n, s.box)
+    q = 2 * math.pi * round(7.25 * s.box / (2 * math.pi)) / s.box
+    t = pool.tcf(0, levels, block, q)
+    with_tcf = chunks(t.sample)
+    lags, vals, terms = t.read()
+    pool.close()
+    dt_s = every * s.dt
+    curve = [{"t": float(lags[a, j] * dt_s), "terms": int(terms[a, j]),
+              "msd_A": vals[a, j, 0, 0], "fs_A": vals[a, j, 0, 2], "vacf_A": vals[a, j, 0, 1]}
+             for a in range(levels) for j in range(block - 1) if terms[a, j]]
+    res = {"particles": n, "steps": steps, "sample_every": every, "levels": levels, "block": block,
+           "q": q, "us_per_step_plain": base / steps * 1e6, "us_per_step_with_tcf": with_tcf / steps * 1e6,
+           "overhead": with_tcf / base - 1.0, "curve": curve}
+    log(json.dumps({k: v for k, v in res.items() if k != "curve"}))
+    return res
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["batch", "serve"])
+    ap.add_argument("mode", choices=["batch", "serve", "tcf"])
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--jobs", type=int, default=40)
@@ -129,6 +181,8 @@ if __name__ == "__main__":
     a = ap.parse_args()
     if a.mode == "batch":
         r = batch(a.replicas, a.steps, precision=a.precision)
+    elif a.mode == "tcf":
+        r = tcf(steps=a.steps, precision=a.precision)
     else:
         r = serve(a.jobs, a.load, a.steps_lo, a.steps_hi, precision=a.precision)
     print(json.dumps(r))

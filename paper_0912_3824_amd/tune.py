@@ -20,7 +20,7 @@ from typing import Dict, List, Optional
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 SPACE = {
-    "step_block": [256, 512],
+    "step_block": [256, 512, 1024],
     "build_width": [4, 8],
     "build_block": [256, 512],
     "build_lanes": [0, 16],

@@ -245,6 +245,20 @@ md_status md_observables(md_system *sys, md_obs *out);
  * host-driven equilibration).  Asynchronous. */
 md_status md_scale_velocities(md_system *sys, int32_t slot, double factor);
 
+/* Modified Andersen thermostat (Sec. 2.3): assign every particle of the
+ * replica at `slot` a Maxwell-Boltzmann velocity at `temperature` (mass from
+ * the configuration), subtract the mean velocity if remove_mean != 0, and
+ * rescale all velocities so that 2 E_kin / (3 N) equals `temperature`
+ * exactly.  Random numbers: rand48 (x -> 0x5DEECE66D x + 0xB mod 2^48)
+ * started from the state srand48(seed) sets (low 32 bits of seed); particle
+ * id i at call `call` uses stream elements i + n (4 call + r), r = 0..3 (a
+ * leap-frog of stride n), turned into three normals by Box-Muller.  Calling
+ * it every (mu dt)^-1 steps with call = 0, 1, 2, ... is the paper's heat
+ * bath of collision rate mu.  The replica must be at a full step.
+ * Asynchronous.  Errors: MD_E_NOSLOT, MD_E_ARG, MD_E_HIP. */
+md_status md_thermostat(md_system *sys, int32_t slot, double temperature, uint64_t seed, int64_t call,
+                        int32_t remove_mean);
+
 /* Benchmark helper: advance every attached replica by n_steps like md_step
  * but with eager launches, timing each step's fused kernel and its group of
  * rebuild kernels with hipEvents recorded on the pool's stream.  The launches

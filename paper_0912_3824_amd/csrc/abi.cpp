@@ -1164,6 +1164,36 @@ md_status md_scale_velocities(md_system *s, int32_t slot, double factor)
     return MD_OK;
 }
 
+md_status md_thermostat(md_system *s, int32_t slot, double temperature, uint64_t seed, int64_t call,
+                        int32_t remove_mean)
+{
+    md_status st = check_slot(s, slot, true);
+    if (st != MD_OK) return st;
+    if (!(temperature > 0) || !std::isfinite(temperature)) return fail(s, MD_E_ARG, "temperature must be positive");
+    if (call < 0 || call > ((int64_t)1 << 40)) return fail(s, MD_E_ARG, "call index out of range");
+    const SlotHost &h = s->slots[slot];
+    int chunk0 = 0; // this slot's first row of chunk partials (4096 particles per chunk)
+    for (int k = 0; k < slot; ++k)
+        if (s->slots[k].attached) chunk0 += (s->slots[k].n + 4095) / 4096;
+    ThermoArgs a;
+    memset(&a, 0, sizeof a);
+    a.A = arena_of(s);
+    a.obs = s->obs;
+    a.partial = s->partial;
+    a.off = (int)h.off;
+    a.n = h.n;
+    a.chunk0 = chunk0;
+    a.nchunk = (h.n + 4095) / 4096;
+    a.remove_mean = remove_mean ? 1 : 0;
+    a.x0 = ((seed & 0xFFFFFFFFULL) << 16) | 0x330EULL; // the state srand48(seed) sets
+    a.call = call;
+    a.temperature = temperature;
+    a.mass = s->cfg.mass;
+    a.scale = std::sqrt(temperature / s->cfg.mass);
+    HIPCHK(s, launch_thermostat(s->prec, a, s->stream));
+    return MD_OK;
+}
+
 md_status md_profile_steps(md_system *s, int64_t n_steps, double *out)
 {
     if (!s || !out) return MD_E_ARG;

@@ -80,6 +80,119 @@ __global__ void k_scale_vel(const ScaleArgs a)
     st.store(a.A, i);
 }
 
+// ------------------------------------------------------------ thermostat
+// rand48 (Sec. 2.3): x_{k+1} = (a x_k + c) mod 2^48.  Element j from x0 is
+// A_j x0 + C_j, the j-fold composition of the affine map, by repeated
+// squaring; particle id i at call k takes elements i + n (4k + r), r = 0..3
+// (the leap-frog of stride n over the particles), so no generator state is
+// stored and the draws do not depend on slot order or launch shape.
+#define R48_A 0x5DEECE66DULL
+#define R48_C 0xBULL
+#define R48_M ((1ULL << 48) - 1ULL)
+
+__device__ __forceinline__ unsigned long long r48_element(unsigned long long x0, unsigned long long j)
+{
+    unsigned long long A = 1, C = 0, a = R48_A, c = R48_C;
+    while (j) {
+        if (j & 1) { A = (a * A) & R48_M; C = (a * C + c) & R48_M; }
+        c = (a * c + c) & R48_M;
+        a = (a * a) & R48_M;
+        j >>= 1;
+    }
+    return (A * x0 + C) & R48_M;
+}
+
+#define TH_CHUNK 4096
+
+// Draw Maxwell-Boltzmann velocities (Box-Muller) into the scratch rows and
+// reduce sum(v) and sum(v^2) per chunk of TH_CHUNK particles.
+__global__ void __launch_bounds__(256) k_thermo_draw(const ThermoArgs a)
+{
+    __shared__ double red[4][256];
+    const int c = blockIdx.x;
+    const int k0 = c * TH_CHUNK, k1 = min(k0 + TH_CHUNK, a.n);
+    double acc[4] = {0, 0, 0, 0};
+    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+        const int i = a.off + k;
+        const int id = a.A.meta[i].w;
+        if (id < 0 || id >= a.n) continue;
+        const unsigned long long base = (unsigned long long)id + (unsigned long long)a.n * (4ULL * a.call);
+        double u[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            u[r] = (double)r48_element(a.x0, base + (unsigned long long)a.n * r) * (1.0 / 281474976710656.0);
+        const double ra = sqrt(-2.0 * log(1.0 - u[0])), rb = sqrt(-2.0 * log(1.0 - u[2]));
+        const double ph = 6.283185307179586 * u[1], ph2 = 6.283185307179586 * u[3];
+        const double v[3] = {a.scale * ra * cos(ph), a.scale * ra * sin(ph), a.scale * rb * cos(ph2)};
+        double *o = a.obs + (size_t)i * 8;
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2];
+        acc[0] += v[0]; acc[1] += v[1]; acc[2] += v[2];
+        acc[3] += v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    }
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) a.partial[(size_t)(a.chunk0 + c) * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Subtract the mean (optional), scale to exactly the bath temperature and
+// store the velocities in the mode's precision.  Every workgroup adds the
+// chunk partials in the same order, so all use the same factor.
+template <int P>
+__global__ void __launch_bounds__(256) k_thermo_apply(const ThermoArgs a)
+{
+    __shared__ double tot[4];
+    if (threadIdx.x < 4) {
+        double t = 0;
+        for (int c = 0; c < a.nchunk; ++c) t += a.partial[(size_t)(a.chunk0 + c) * 8 + threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const double n = (double)a.n;
+    double mean[3] = {0, 0, 0};
+    if (a.remove_mean)
+        for (int d = 0; d < 3; ++d) mean[d] = tot[d] / n;
+    const double ss = tot[3] - n * (mean[0] * mean[0] + mean[1] * mean[1] + mean[2] * mean[2]);
+    const double f = sqrt(a.temperature / (a.mass * ss / (3.0 * n)));
+    const int i = a.off + k;
+    const double *o = a.obs + (size_t)i * 8;
+    const double v[3] = {(o[0] - mean[0]) * f, (o[1] - mean[1]) * f, (o[2] - mean[2]) * f};
+    State<P> st;
+    st.load(a.A, i);
+    if constexpr (P == PREC_FP32) {
+        st.vx = (float)v[0]; st.vy = (float)v[1]; st.vz = (float)v[2];
+    } else if constexpr (P == PREC_DS) {
+        dsf *w[3] = {&st.vx, &st.vy, &st.vz};
+        for (int d = 0; d < 3; ++d) {
+            w[d]->hi = (float)v[d];
+            w[d]->lo = (float)(v[d] - (double)w[d]->hi);
+        }
+    } else {
+        st.vx = v[0]; st.vy = v[1]; st.vz = v[2];
+    }
+    st.store(a.A, i);
+}
+
+hipError_t launch_thermostat(int prec, const ThermoArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_thermo_draw, dim3(a.nchunk), dim3(256), 0, s, a);
+    const int grid = (a.n + 255) / 256;
+    switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((k_thermo_apply<PREC_FP32>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_DS: hipLaunchKernelGGL((k_thermo_apply<PREC_DS>), dim3(grid), dim3(256), 0, s, a); break;
+    case PREC_MIX: hipLaunchKernelGGL((k_thermo_apply<PREC_MIX>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_thermo_apply<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------ k_ds_eval
 __global__ void k_ds_eval(int op, long long n, const float *a, const float *b, float *out)
 {

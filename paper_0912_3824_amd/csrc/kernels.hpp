@@ -108,6 +108,20 @@ struct ScaleArgs {
     double fd;
 };
 
+// Modified Andersen thermostat (Sec. 2.3): rand48 draws, leap-frogged with
+// stride n over the replica's particles.
+struct ThermoArgs {
+    KArena A;
+    double *obs;      // per-slot scratch rows (8 doubles); velocities drawn here
+    double *partial;  // chunk partial sums (8 doubles per chunk)
+    int off, n, chunk0, nchunk, remove_mean, pad0;
+    unsigned long long x0; // rand48 state of the seed (stream element 0)
+    long long call;        // thermostat call index
+    double scale;          // sqrt(T / m)
+    double temperature, mass;
+};
+
+hipError_t launch_thermostat(int prec, const ThermoArgs &a, hipStream_t s);
 hipError_t launch_step(int prec, const StepArgs &a, int block, bool obs, hipStream_t s);
 hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);

@@ -34,7 +34,7 @@ EXPORTS = [
     "md_save", "md_restore", "md_debug_neighbours", "md_get_launch",
     "md_set_launch", "md_ds_eval", "md_strerror", "md_last_error",
     "md_abi_version", "md_tcf_workspace_bytes", "md_tcf_create", "md_tcf_sample",
-    "md_tcf_read", "md_tcf_destroy",
+    "md_tcf_read", "md_tcf_destroy", "md_thermostat",
 ]
 
 
@@ -139,6 +139,7 @@ def load():
         "md_tcf_sample": (i32, [vp]),
         "md_tcf_read": (i32, [vp, i64p, dp, i64p]),
         "md_tcf_destroy": (None, [vp]),
+        "md_thermostat": (i32, [vp, i32, ctypes.c_double, ctypes.c_uint64, i64, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -290,6 +291,26 @@ class MdSystem:
         if getattr(self, "h", None):
             self.lib.md_destroy(self.h)
             self.h = None
+
+    def thermostat(self, slot: int, temperature: float, seed: int, call: int, remove_mean: bool = True):
+        """Modified Andersen thermostat call (md_thermostat): Maxwell-Boltzmann
+        velocities from the leap-frogged rand48 stream, rescaled to exactly T."""
+        self._check(self.lib.md_thermostat(self.h, int(slot), float(temperature), int(seed) & (2 ** 64 - 1),
+                                           int(call), 1 if remove_mean else 0), "md_thermostat")
+
+    def andersen(self, slot: int, temperature: float, mu: float, steps: int, seed: int, first_call: int = 0):
+        """Advance `steps` steps with the heat bath of collision rate mu: a
+        thermostat call every (mu dt)^-1 steps (Sec. 2.3).  Returns the next
+        call index."""
+        every = max(1, int(round(1.0 / (mu * self.cfg.dt))))
+        call, done = first_call, 0
+        while done < steps:
+            self.thermostat(slot, temperature, seed, call)
+            call += 1
+            k = min(every, steps - done)
+            self.step(k)
+            done += k
+        return call
 
     def tcf(self, slot: int, levels: int, block: int, q: float) -> "Tcf":
         """A blocking scheme for time-correlation functions bound to `slot`

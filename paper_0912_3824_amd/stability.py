@@ -12,10 +12,11 @@ g(x) = x^4 / (1 + x^4), in single, double-single and double precision.
             centre-of-mass speed |sum v|/N reached (Sec. 4.1).
   speed:    particle-steps/s of WCA against LJ (Sec. 4: shorter lists).
 
-All runs of one potential start from the same state: an fcc lattice
-equilibrated by velocity rescaling in double precision with h = 0.005 (the
-paper equilibrates with an Andersen thermostat; the thermostat is not part
-of this build).  System: N = 10,000, rho = 0.75, T = 1.12, as in Sec. 4.
+All runs of one potential start from the same state, prepared as Sec. 4
+describes: an fcc lattice equilibrated in the heat bath of the modified
+Andersen thermostat (Sec. 2.3, collision rate mu = 1) with dt = 0.001 and
+h = 0.005 over 1e5 steps in double-single precision.  System: N = 10,000,
+rho = 0.75, T = 1.12.
 
   python -m paper_0912_3824_amd.stability [--steps 200000] [--n 10000]
 """
@@ -40,18 +41,14 @@ def log(*a):
 
 
 def equilibrated(n: int, rc: float, rho: float, temperature: float, steps: int, seed: int):
-    """Lattice start equilibrated by velocity rescaling (FP64, h = 0.005)."""
+    """Lattice start equilibrated in the Andersen heat bath (mu = 1, dt = 0.001,
+    h = 0.005, double-single), as in Sec. 4."""
     import md_inputs as I
     from paper_0912_3824_amd import mdx
     s = I.smoothed(I.make_lj(n, rho=rho, temperature=temperature, seed=seed, jitter=0.05, rc=rc), 0.005)
-    s = dataclasses.replace(s, dt=0.002)
-    pool = mdx.md_init([s], "fp64")
-    done = 0
-    while done < steps:
-        pool.step(100)
-        done += 100
-        o = pool.observables()[0]
-        pool.scale_velocities(0, math.sqrt(temperature / o["temperature"]))
+    s = dataclasses.replace(s, dt=0.001)
+    pool = mdx.md_init([s], "ds")
+    pool.andersen(0, temperature, mu=1.0, steps=steps, seed=seed)
     pos, vel, _ = pool.get_state(0)
     pool.close()
     return dataclasses.replace(s, pos=pos, vel=vel)
@@ -134,7 +131,7 @@ def speed(s, prec="ds", steps=2000) -> dict:
             "mean_list_entries": o["list_entries"] / s.n}
 
 
-def run(n=10000, rho=0.75, temperature=1.12, equil=20000, drift_steps=200000, seed=20240101) -> dict:
+def run(n=10000, rho=0.75, temperature=1.12, equil=100000, drift_steps=200000, seed=20240101) -> dict:
     import md_inputs as I
     res = {"n": n, "rho": rho, "temperature": temperature, "equil_steps": equil}
     states = {}
@@ -155,7 +152,7 @@ def run(n=10000, rho=0.75, temperature=1.12, equil=20000, drift_steps=200000, se
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=10000)
-    ap.add_argument("--equil", type=int, default=20000)
+    ap.add_argument("--equil", type=int, default=100000)
     ap.add_argument("--steps", type=int, default=200000, help="steps per drift run")
     a = ap.parse_args()
     print(json.dumps(run(n=a.n, equil=a.equil, drift_steps=a.steps)))

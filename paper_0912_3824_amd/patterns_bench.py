@@ -5,6 +5,7 @@ results).
   python -m paper_0912_3824_amd.patterns_bench batch [--replicas 256 --steps 2000]
   python -m paper_0912_3824_amd.patterns_bench serve [--jobs 40 --load 0.8]
   python -m paper_0912_3824_amd.patterns_bench tcf   [--steps 3000]
+  python -m paper_0912_3824_amd.patterns_bench thermo [--steps 3000]
 
 batch: 256 Kob-Andersen replicas, N log-uniform in [500, 8000], rho = 1.2,
        T from {0.45, 0.5, 0.6, 0.8}, advanced together in one pool (one
@@ -13,6 +14,9 @@ batch: 256 Kob-Andersen replicas, N log-uniform in [500, 8000], rho = 1.2,
 tcf:   the N = 1M KA run with on-device time-correlation functions
        (blocking scheme, Sec. 2.5) sampled every 10 steps, against the same
        run without them.
+thermo: the N = 1M KA run in the heat bath of the modified Andersen
+       thermostat (Sec. 2.3): the cost of one thermostat call, and the same
+       run with a call every (mu dt)^-1 steps against the run without.
 serve: Poisson arrivals of KA jobs, N log-uniform in [1000, 256000], steps
        uniform in [steps_lo, steps_hi], T uniform in [0.45, 1.0]; admission
        by arena footprint; p50/p99 latency and throughput over the busy
@@ -168,9 +172,45 @@ def tcf(n=1_000_000, steps=3000, every=10, levels=4, block=10, precision="ds", s
     return res
 
 
+def thermo(n=1_000_000, steps=3000, calls=100, mu=1.0, precision="ds", seed=20240101):
+    """Cost of the modified Andersen thermostat at the N = 1M KA workload:
+    `calls` back-to-back calls, and `steps` steps with and without the bath
+    (a call every (mu dt)^-1 steps)."""
+    import torch
+    import md_inputs as I
+    from paper_0912_3824_amd import mdx
+    s = I.make_ka(n, 0.5, seed=seed)
+    pool = mdx.md_init([s], precision)
+    pool.step(200)
+    for c in range(5):  # warm-up
+        pool.thermostat(0, 0.5, seed, c)
+    pool.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(calls):
+        pool.thermostat(0, 0.5, seed, 5 + c)
+    pool.sync()
+    per_call = (time.perf_counter() - t0) / calls
+    base = _timed_step(pool, steps)
+    pool.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pool.andersen(0, 0.5, mu=mu, steps=steps, seed=seed, first_call=1000)
+    pool.sync()
+    bath = time.perf_counter() - t0
+    o = pool.observables()[0]
+    pool.close()
+    res = {"particles": n, "precision": precision, "us_per_call": per_call * 1e6,
+           "every": int(round(1.0 / (mu * s.dt))), "steps": steps,
+           "us_per_step_plain": base / steps * 1e6, "us_per_step_bath": bath / steps * 1e6,
+           "overhead": bath / base - 1.0, "temperature_after": o["temperature"]}
+    log(json.dumps(res))
+    return res
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["batch", "serve", "tcf"])
+    ap.add_argument("mode", choices=["batch", "serve", "tcf", "thermo"])
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--jobs", type=int, default=40)
@@ -183,6 +223,8 @@ if __name__ == "__main__":
         r = batch(a.replicas, a.steps, precision=a.precision)
     elif a.mode == "tcf":
         r = tcf(steps=a.steps, precision=a.precision)
+    elif a.mode == "thermo":
+        r = thermo(steps=a.steps, precision=a.precision)
     else:
         r = serve(a.jobs, a.load, a.steps_lo, a.steps_hi, precision=a.precision)
     print(json.dumps(r))

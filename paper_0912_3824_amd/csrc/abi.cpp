@@ -597,7 +597,7 @@ struct HostRep {
     std::vector<uint4> st[3];
     std::vector<uint4> snap; // NS * n
     std::vector<int4> meta;
-    std::vector<int> cs;     // ncell + 1, absolute
+    std::vector<int> cs;     // planes * ncell + 1, absolute
 };
 
 static void put_dbl2(uint4 &u, double a, double b)
@@ -630,6 +630,7 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     r.off = (int)h.off;
     r.nd = h.nd;
     r.coff = (int)h.coff;
+    r.planes = s->cfg.n_species;
     r.L = h.L;
     r.invL = 1.0 / h.L;
     r.fxs = 4294967296.0 / h.L;
@@ -637,7 +638,7 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     r.Lf = (float)h.L;
     r.L_hi = (float)h.L;
     r.L_lo = (float)(h.L - (double)r.L_hi);
-    r.items3 = h.nd * h.nd * h.nd;
+    r.items3 = h.nd * h.nd * h.nd; // a sort work item covers a cell in every plane
     r.items4 = items4_of(s, h.n, h.nd);
     build_shape(s, h.n, h.nd, r.bparts, r.blanes);
     return r;
@@ -752,7 +753,7 @@ static md_status alloc_slot_ranges(md_system *s, int slot, int n, double L, Slot
     int64_t ncell = (int64_t)h.nd * h.nd * h.nd;
     if (ncell > (int64_t)1 << 30) return fail(s, MD_E_ARG, "too many cells");
     if (!s->parena.alloc(n, h.off)) return fail(s, MD_E_CAPACITY, "particle arena full (need %d)", n);
-    h.ncell_alloc = ncell + 1;
+    h.ncell_alloc = s->cfg.n_species * ncell + 1; // a cell range per species plane
     if (!s->carena.alloc(h.ncell_alloc, h.coff)) {
         s->parena.release(h.off, n);
         return fail(s, MD_E_CAPACITY, "cell arena full (need %lld)", (long long)h.ncell_alloc);
@@ -938,10 +939,10 @@ md_status md_attach(md_system *s, int32_t slot, const md_replica *rep, const int
         uint32_t m = meta_word(slot, species ? species[k] : 0);
         encode_particle(s, r, x, v, img, m, &w[3 * (size_t)k], &sn[2 * (size_t)k]);
         mt[k] = make_int4(img[0], img[1], img[2], k);
-        cell[k] = cell_of_snap(s, r, &sn[2 * (size_t)k]);
+        cell[k] = sort_key(cell_of_snap(s, r, &sn[2 * (size_t)k]), m, r.planes, r.nd);
     }
-    // stable counting sort by cell
-    const int ncell = h.nd * h.nd * h.nd;
+    // stable counting sort by species plane and cell
+    const int ncell = r.planes * h.nd * h.nd * h.nd;
     HostRep hr;
     hr.cs.assign(ncell + 1, 0);
     for (int k = 0; k < n; ++k) hr.cs[cell[k] + 1]++;
@@ -1446,7 +1447,7 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
     hr.meta.resize(n);
     memcpy(hr.meta.data(), b, 16 * n);
     // re-tag the slot in the meta words and recover the cell starts
-    const int ncell = h.nd * h.nd * h.nd;
+    const int ncell = r.planes * h.nd * h.nd * h.nd;
     hr.cs.assign(ncell + 1, 0);
     int prev = 0;
     for (int64_t k = 0; k < n; ++k) {
@@ -1460,7 +1461,13 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
             }
         }
         uint4 sn[2] = {xr[k], H.NS == 2 ? xr[n + k] : make_uint4(0, 0, 0, 0)};
-        int c = cell_of_snap(s, r, sn);
+        uint32_t mw = sn[0].w;
+        if (H.NS == 2) {
+            double z, w;
+            get_dbl2(sn[1], z, w);
+            mw = meta_of_bits(w);
+        }
+        int c = sort_key(cell_of_snap(s, r, sn), mw, r.planes, r.nd);
         if (c < prev) { release_slot_ranges(s, h); return fail(s, MD_E_ARG, "checkpoint order is not by cell"); }
         prev = c;
         hr.cs[c + 1]++;

@@ -14,9 +14,13 @@
 //                fixed-point snapshot of the new position, displacement test
 //                against the list's reference position, and the count of the
 //                particle's new cell (for the sort, Sec. 2.2 cell binning).
+//                The sort key is the cell within the particle's species
+//                plane: a binary mixture is stored as all A particles by
+//                cell, then all B particles by cell.
 //   k_scan       per replica: exclusive scan of the cell counts -> cell starts.
-//   k_permute<P> per cell (one wave): stable counting-sort scatter.  Members
-//                of a new cell come from the 27 surrounding old cells (a
+//   k_permute<P> per cell of a plane (one wave): stable counting-sort
+//                scatter.  Members of a new cell come from the 27
+//                surrounding old cells of the same plane (a
 //                particle moves less than one cell between builds); a ballot
 //                over them in old slot order gives each its new slot.  The
 //                whole particle record is gathered into the scratch arena,
@@ -28,7 +32,7 @@
 //                copied back from scratch.
 //
 // Bitwise determinism: lists are in a canonical order (own cell, then +o/-o
-// pairs, slot order inside a cell), the sort is stable, each particle sums
+// pairs; inside a cell the A members, then the B members, in slot order), the sort is stable, each particle sums
 // its own list sequentially, and no floating-point atomics are used.  The
 // result for a replica therefore does not depend on launch shapes or on
 // other replicas in the pool.

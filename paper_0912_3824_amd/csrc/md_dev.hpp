@@ -36,7 +36,8 @@ struct RepDev {
     int n;        // particles
     int off;      // first particle slot in the arena
     int nd;       // cells per box edge (1 = single-cell mode)
-    int coff;     // first cell in the cell arena (nd^3 + 1 entries reserved)
+    int coff;     // first cell in the cell arena (planes * nd^3 + 1 entries reserved)
+    int planes;   // species planes of the sort key (1, or 2 for a binary mixture)
     double L;     // box edge
     double invL;  // 1 / L
     double fxs;   // 2^32 / L   (double -> fixed point)
@@ -136,6 +137,15 @@ __host__ __device__ __forceinline__ int dbl_cell1(double x, double L, double inv
     if (c < 0) c = 0;
     if (c >= nd) c = nd - 1;
     return c;
+}
+
+// Sort key of a particle (its index in the replica's cell arrays): the cell
+// within the plane of its species.  With two planes every species is sorted
+// by cell on its own (all A, then all B), so a wave of the force kernel
+// holds particles of one species, whose lists are of similar length.
+__host__ __device__ __forceinline__ int sort_key(int cell, uint32_t meta, int planes, int nd)
+{
+    return planes > 1 ? (int)(meta & SPECIES_MASK) * nd * nd * nd + cell : cell;
 }
 
 __host__ __device__ __forceinline__ int dbl_cell(double x, double y, double z, double L, double invL, int nd)

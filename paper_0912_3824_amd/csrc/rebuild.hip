@@ -26,13 +26,17 @@ __global__ void k_count(const CountArgs a)
     int cell;
     if (NS == 2) cell = dbl_cell(x, y, z, rp.L, rp.invL, rp.nd);
     else cell = rp.nd == 1 ? 0 : fixed_cell(s0.x, s0.y, s0.z, rp.nd);
-    atomicAdd(a.count + rp.coff + cell, 1);
+    atomicAdd(a.count + rp.coff + sort_key(cell, meta, rp.planes, rp.nd), 1);
 }
 
 // ------------------------------------------------------------ k_scan
 // One workgroup (1024 threads) per slot: exclusive scan of the cell counts
-// in tiles of 8 cells per thread, cell starts written as absolute slots.
-__global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
+// (every species plane, in order), cell starts written as absolute slots.
+// Tiles of SCAN_CPT x 1024 cells pass through LDS, so that global reads and
+// writes are coalesced while each thread scans SCAN_CPT consecutive cells.
+#define SCAN_CPT 8
+#define SCAN_B 1024
+__global__ void __launch_bounds__(SCAN_B) k_scan(const ScanArgs a)
 {
     int s = blockIdx.x;
     if (a.force_slot == -1) {
@@ -43,21 +47,27 @@ __global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
         if (!slot_selected(s, a.force_slot, a.need, a.ctl)) return;
     }
     const RepDev rp = a.rep[s];
-    const int ncell = rp.nd * rp.nd * rp.nd;
-    const int B = blockDim.x, t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6, nw = (B + 63) >> 6;
+    const int ncell = rp.planes * rp.nd * rp.nd * rp.nd;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6, nw = SCAN_B >> 6;
     const int *cnt = a.count + rp.coff;
     int *out = a.cs_new + rp.coff;
-    __shared__ int wsum[16];
+    __shared__ int tile[SCAN_CPT * SCAN_B];
+    __shared__ int wsum[SCAN_B / 64];
     __shared__ int tile_total;
     int carry = 0;
-    for (int base = 0; base < ncell; base += 8 * B) {
-        int v[8];
+    for (int base = 0; base < ncell; base += SCAN_CPT * SCAN_B) {
+#pragma unroll
+        for (int u = 0; u < SCAN_CPT; ++u) {
+            const int c = base + u * SCAN_B + t;
+            tile[u * SCAN_B + t] = c < ncell ? cnt[c] : 0;
+        }
+        __syncthreads();
+        int v[SCAN_CPT];
         int local = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int c = base + 8 * t + u;
-            v[u] = c < ncell ? cnt[c] : 0;
+        for (int u = 0; u < SCAN_CPT; ++u) {
+            v[u] = tile[SCAN_CPT * t + u];
             local += v[u];
         }
         int incl = local;
@@ -76,10 +86,15 @@ __global__ void __launch_bounds__(1024) k_scan(const ScanArgs a)
         __syncthreads();
         int run = rp.off + carry + wsum[wv] + incl - local;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int c = base + 8 * t + u;
-            if (c < ncell) out[c] = run;
+        for (int u = 0; u < SCAN_CPT; ++u) {
+            tile[SCAN_CPT * t + u] = run;
             run += v[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SCAN_CPT; ++u) {
+            const int c = base + u * SCAN_B + t;
+            if (c < ncell) out[c] = tile[u * SCAN_B + t];
         }
         carry += tile_total;
         __syncthreads();
@@ -199,51 +214,57 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6;
-    __shared__ int pref[4][28], pst[4][27];
+    __shared__ int pref[4][55], pst[4][54];
     for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 3,
               blockIdx.x * wpb + wv, gridDim.x * wpb, [&](int s, int c) {
         const RepDev rp = a.rep[s];
-        const int nd = rp.nd;
+        const int nd = rp.nd, nc = nd * nd * nd, planes = rp.planes;
         const int *cs = a.cs + rp.coff;
-        const int dst0 = a.cs_new[rp.coff + c];
-        const int want = a.cs_new[rp.coff + c + 1] - dst0;
-        // the old cells that can hold members of new cell c, ascending (so
-        // that the flattened candidates are in old slot order)
-        int nold = 1;
-        if (lane == 0) { pst[wv][0] = cs[0]; pref[wv][0] = 0; pref[wv][1] = cs[1] - cs[0]; }
-        if (nd > 1) {
-            nold = 27;
-            const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
-            int v[3][3] = {{(cx + nd - 1) % nd, cx, (cx + 1) % nd},
-                           {(cy + nd - 1) % nd, cy, (cy + 1) % nd},
-                           {(cz + nd - 1) % nd, cz, (cz + 1) % nd}};
+        // new cell c of every plane: plane-0 members go to [dst0, dst0 +
+        // want0), plane-1 members to [dst1, dst1 + want1)
+        const int dst0 = a.cs_new[rp.coff + c], want0 = a.cs_new[rp.coff + c + 1] - dst0;
+        const int dst1 = planes > 1 ? a.cs_new[rp.coff + nc + c] : 0;
+        const int want1 = planes > 1 ? a.cs_new[rp.coff + nc + c + 1] - dst1 : 0;
+        // the old cells that can hold members of new cell c: plane 0's in
+        // ascending order, then plane 1's (so that the flattened candidates
+        // are in old slot order); one range per lane
+        const int nold = nd == 1 ? 1 : 27, nr = planes * nold;
+        int len = 0, st0 = 0;
+        if (lane < nr) {
+            const int pl = lane >= nold, kk = lane - pl * nold;
+            int oc = 0;
+            if (nd > 1) {
+                const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
+                int v[3][3] = {{(cx + nd - 1) % nd, cx, (cx + 1) % nd},
+                               {(cy + nd - 1) % nd, cy, (cy + 1) % nd},
+                               {(cz + nd - 1) % nd, cz, (cz + 1) % nd}};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                int *u = v[d];
-                if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
-                if (u[1] > u[2]) { int t = u[1]; u[1] = u[2]; u[2] = t; }
-                if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+                for (int d = 0; d < 3; ++d) {
+                    int *u = v[d];
+                    if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+                    if (u[1] > u[2]) { int t = u[1]; u[1] = u[2]; u[2] = t; }
+                    if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
+                }
+                const int kx = kk % 3, ky = (kk / 3) % 3, kz = kk / 9;
+                oc = v[0][kx] + nd * (v[1][ky] + nd * v[2][kz]);
             }
-            int len = 0, st0 = 0;
-            if (lane < 27) {
-                const int kx = lane % 3, ky = (lane / 3) % 3, kz = lane / 9;
-                const int oc = v[0][kx] + nd * (v[1][ky] + nd * v[2][kz]);
-                st0 = cs[oc];
-                len = cs[oc + 1] - st0;
-            }
-            int incl = len;
-#pragma unroll
-            for (int o = 1; o < 32; o <<= 1) {
-                const int u = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += u;
-            }
-            if (lane < 27) { pst[wv][lane] = st0; pref[wv][lane + 1] = incl; }
-            if (lane == 0) pref[wv][0] = 0;
+            oc += pl * nc;
+            st0 = cs[oc];
+            len = cs[oc + 1] - st0;
         }
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane < nr) { pst[wv][lane] = st0; pref[wv][lane + 1] = incl; }
+        if (lane == 0) pref[wv][0] = 0;
         __builtin_amdgcn_wave_barrier();
-        const int tot = pref[wv][nold];
-        int run = 0;
-        int r = 0; // old cell of the lane's current candidate (only moves forward)
+        const int tot = pref[wv][nr], tot0 = pref[wv][nold];
+        int run0 = 0, run1 = 0;
+        int r = 0; // range of the lane's current candidate (only moves forward)
+        const unsigned long long below = (1ull << lane) - 1ull;
         constexpr int U = 4; // candidates per lane per pass
         for (int b = 0; b < tot; b += 64 * U) {
             int q[U];
@@ -253,7 +274,7 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
                 const int e = b + 64 * u + lane;
                 q[u] = -1;
                 if (e < tot) {
-                    while (r + 1 < nold && pref[wv][r + 1] <= e) ++r;
+                    while (r + 1 < nr && pref[wv][r + 1] <= e) ++r;
                     q[u] = pst[wv][r] + (e - pref[wv][r]);
                 }
             }
@@ -265,34 +286,47 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
                 if (m[u]) move_load<P>(a, q[u], mv[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const unsigned long long bal = __ballot(m[u]);
-                if (m[u]) move_store<P>(a, rp, mv[u], dst0 + run + __popcll(bal & ((1ull << lane) - 1ull)));
-                run += __popcll(bal);
+                const bool p1 = b + 64 * u + lane >= tot0;
+                const unsigned long long bal0 = __ballot(m[u] && !p1), bal1 = __ballot(m[u] && p1);
+                if (m[u])
+                    move_store<P>(a, rp, mv[u], p1 ? dst1 + run1 + __popcll(bal1 & below)
+                                                   : dst0 + run0 + __popcll(bal0 & below));
+                run0 += __popcll(bal0);
+                run1 += __popcll(bal1);
             }
         }
         // every particle counted in this cell must have come from a
         // neighbouring old cell; a shortfall means a particle jumped further
-        if (lane == 0 && run != want) atomicOr(a.status + s, 4);
+        if (lane == 0 && (run0 != want0 || run1 != want1)) atomicOr(a.status + s, 4);
         __builtin_amdgcn_wave_barrier();
     });
 }
 
 // ------------------------------------------------------------ k_build
 // One workgroup per row segment of cells (cells x0..x1-1 of row (y, z)):
-// the 9 neighbouring rows over x0-1..x1 are staged in LDS, then every member
-// writes its list in the canonical order.
+// the 9 neighbouring rows over x0-1..x1 are staged in LDS, each cell's
+// plane-0 members followed by its plane-1 members, then every member of the
+// segment (of either plane) writes its list in the canonical order: the own
+// cell, then each half-space offset o followed by -o, and within each cell
+// the A members before the B members, in slot order.
 #define BUILD_LDS_CAP 3072 // staged candidates (x 16 B = 48 KB, fixed point)
 #define BUILD_MAX_NX 18    // cells per staged row (width + 2 halo)
 #define BUILD_TAB (9 * BUILD_MAX_NX)
 
 struct BuildTabs {
-    int start[BUILD_TAB]; // LDS start of staged cell (global start when not staged)
-    int cnt[BUILD_TAB];
-    int glob[BUILD_TAB];  // global start of the cell
-    int4 pk[BUILD_TAB];   // (start, cnt, glob) of each staged cell, for the grouped scan
-    int run_lds[19], run_glob[19];
-    int nruns, total, fits, NX;
+    // staged cell k = row * NX + lx: (LDS start of its members, members of
+    // both planes, global start in plane 0, global start in plane 1)
+    int4 pk[BUILD_TAB];
+    int na[BUILD_TAB]; // members in plane 0
+    int ncell, total, fits, NX;
 };
+
+// Candidate e of a staged cell: plane-0 member e, else plane-1 member e - na
+// (its global slot), and where it is read from (LDS, or the arena when the
+// neighbourhood did not fit).
+__device__ __forceinline__ int cand_glob(const int4 &c, int na, int e) { return e < na ? c.z + e : c.w + (e - na); }
+template <bool FROM_LDS>
+__device__ __forceinline__ int cand_at(const int4 &c, int na, int e) { return FROM_LDS ? c.x + e : cand_glob(c, na, e); }
 
 template <int P, bool FROM_LDS>
 __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
@@ -324,15 +358,16 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
     int *col = A.nbr_w + 4 * (size_t)i;
     const size_t row_stride = 4 * P_;
     int cnt = 0;
-    // a candidate's snapshot (two words for double snapshots), then the test
+    // a candidate's snapshot (two words for double snapshots) at staged
+    // index x (a global slot when nothing is staged), then the test
     struct Cand { uint4 a, b; };
-    auto load = [&](int e, int st) -> Cand {
+    auto load = [&](int x) -> Cand {
         Cand q;
         if (NS == 2) {
-            q.a = FROM_LDS ? cand[2 * (st + e)] : a.src_x[st + e];
-            q.b = FROM_LDS ? cand[2 * (st + e) + 1] : a.src_x[P_ + st + e];
+            q.a = FROM_LDS ? cand[2 * x] : a.src_x[x];
+            q.b = FROM_LDS ? cand[2 * x + 1] : a.src_x[P_ + x];
         } else {
-            q.a = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+            q.a = FROM_LDS ? cand[x] : a.src_x[x];
             q.b = q.a;
         }
         return q;
@@ -355,22 +390,24 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
         return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
     };
-    auto test = [&](int e, int st) -> bool { return eval(load(e, st)); };
-    // Candidates of one cell in slot order; `self` is the candidate index of
-    // i in this cell, or -1.  Each chunk of up to 64 candidates is tested
-    // four at a time (independent reads in flight, no stores and no branches
-    // in the test loop: a wave would otherwise run the store path whenever
-    // any of its lanes accepts) into an acceptance mask, whose set bits are
-    // then stored in slot order.
-    auto scan_cell = [&](int k, int self) {
-        const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
+    // The candidates of staged cell k in order (i itself is skipped).  Each
+    // chunk of up to 64 candidates is tested four at a time (independent
+    // reads in flight, no stores and no branches in the test loop: a wave
+    // would otherwise run the store path whenever any of its lanes accepts)
+    // into an acceptance mask, whose set bits are then stored in order.
+    auto scan_cell = [&](int k) {
+        const int4 c = T.pk[k];
+        const int na = T.na[k], n = c.y;
+        auto at = [&](int e) { return cand_at<FROM_LDS>(c, na, e); };
+        const int self = (unsigned)(i - c.z) < (unsigned)na ? i - c.z
+                       : (unsigned)(i - c.w) < (unsigned)(n - na) ? na + (i - c.w) : -1;
         for (int base = 0; base < n; base += 64) {
             const int m = min(64, n - base), last = base + m - 1;
             unsigned long long mask = 0;
             for (int e = 0; e < m; e += 4) {
                 // past the chunk's end: re-test its last candidate, masked off
-                const Cand q0 = load(base + e, st), q1 = load(min(base + e + 1, last), st),
-                           q2 = load(min(base + e + 2, last), st), q3 = load(min(base + e + 3, last), st);
+                const Cand q0 = load(at(base + e)), q1 = load(at(min(base + e + 1, last))),
+                           q2 = load(at(min(base + e + 2, last))), q3 = load(at(min(base + e + 3, last)));
                 const bool c0 = eval(q0);
                 const bool c1 = eval(q1) && e + 1 < m;
                 const bool c2 = eval(q2) && e + 2 < m;
@@ -382,14 +419,14 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             while (mask) {
                 const int b = __ffsll((long long)mask) - 1;
                 mask &= mask - 1;
-                if (cnt < cap) col[4 * ((unsigned long long)(unsigned)(cnt >> 2) * (unsigned)P_) + (cnt & 3)] = g0 + base + b;
+                if (cnt < cap) col[4 * ((unsigned long long)(unsigned)(cnt >> 2) * (unsigned)P_) + (cnt & 3)] = cand_glob(c, na, base + b);
                 ++cnt;
             }
         }
     };
     int last_cell = 0;
     if (nd == 1) {
-        scan_cell(0, i - T.glob[0]);
+        scan_cell(0);
     } else {
         // own cell, then each half-space offset o followed by -o: in the
         // (dz, dy, dx) enumeration of the 27 offsets the positive half space
@@ -399,31 +436,29 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
             return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
         };
-        const int own = cell_k(0, 0, 0);
-        scan_cell(own, i - T.glob[own]);
+        scan_cell(cell_k(0, 0, 0));
         for (int q = 14; q < 27; ++q) {
             const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
-            scan_cell(cell_k(dx, dy, dz), -1);
+            scan_cell(cell_k(dx, dy, dz));
             last_cell = cell_k(-dx, -dy, -dz);
-            scan_cell(last_cell, -1);
+            scan_cell(last_cell);
         }
     }
     // Pad the list to a multiple of 8 with a particle that is outside the
     // list radius at this build: it stays beyond the force cutoff until the
     // next build (each particle moves at most skin/2), so the force loop
     // needs no per-entry validity test.  The pad is the first rejected
-    // candidate of the last cell visited (a corner cell), else of any cell.
+    // candidate of the last cell visited (a corner cell), else of any
+    // staged cell.
     if (cnt & 7) {
         int pad = -1;
-        {
-            const int st = T.start[last_cell], n = T.cnt[last_cell], g0 = T.glob[last_cell];
-            for (int e = 0; e < n && pad < 0; ++e)
-                if (!test(e, st) && g0 + e != i) pad = g0 + e;
-        }
-        for (int k = 0; k < (nd == 1 ? 1 : 9 * NX) && pad < 0; ++k) {
-            const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
-            for (int e = 0; e < n && pad < 0; ++e)
-                if (!test(e, st) && g0 + e != i) pad = g0 + e;
+        for (int k = 0, kk = last_cell; k <= T.ncell && pad < 0; kk = k++) {
+            const int4 c = T.pk[kk];
+            const int na = T.na[kk];
+            for (int e = 0; e < c.y && pad < 0; ++e) {
+                const int g = cand_glob(c, na, e);
+                if (!eval(load(cand_at<FROM_LDS>(c, na, e))) && g != i) pad = g;
+            }
         }
         if (pad < 0) atomicOr(a.status + s, 8);
         for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
@@ -469,15 +504,16 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
     const int cap = A.cap;
     int *col = A.nbr_w + 4 * (size_t)i;
     const size_t row_stride = 4 * P_;
-    auto test = [&](int e, int st) -> bool {
+    // test the candidate at staged index x (a global slot when nothing is staged)
+    auto test = [&](int x) -> bool {
         if (NS == 2) {
             double xj, yj, zj, wj;
             if (FROM_LDS) {
-                u4_to_dbl2(cand[2 * (st + e)], xj, yj);
-                u4_to_dbl2(cand[2 * (st + e) + 1], zj, wj);
+                u4_to_dbl2(cand[2 * x], xj, yj);
+                u4_to_dbl2(cand[2 * x + 1], zj, wj);
             } else {
-                u4_to_dbl2(a.src_x[st + e], xj, yj);
-                u4_to_dbl2(a.src_x[P_ + st + e], zj, wj);
+                u4_to_dbl2(a.src_x[x], xj, yj);
+                u4_to_dbl2(a.src_x[P_ + x], zj, wj);
             }
             double dx = xd - xj, dy = yd - yj, dz = zd - zj;
             dx -= rp.L * rint(dx * rp.invL);
@@ -486,31 +522,34 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
             const double r2 = dx * dx + dy * dy + dz * dz;
             return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
         }
-        const uint4 xj = FROM_LDS ? cand[st + e] : a.src_x[st + e];
+        const uint4 xj = FROM_LDS ? cand[x] : a.src_x[x];
         const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
                     dz = (float)(int)(xi.z - xj.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
         return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
     };
-    // one cell's candidates, 4G at a time: lane gl tests e = b + u G + gl
-    // (u = 0..3, independent loads in flight); the ballots are taken in u
-    // order, which is ascending e
+    // one cell's candidates (in the one-lane build's order), 4G at a time:
+    // lane gl tests e = b + u G + gl (u = 0..3, independent loads in
+    // flight); the ballots are taken in u order, which is ascending e
     int cnt = 0;
     auto scan_cell = [&](int k) {
-        const int4 c = T.pk[k]; // (start, cnt, glob)
-        for (int b = 0; b < c.y; b += 4 * G) {
+        const int4 c = T.pk[k];
+        const int na = T.na[k], n = c.y;
+        for (int b = 0; b < n; b += 4 * G) {
             bool acc[4];
+            int g[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) { // past the end: test the last candidate, masked off
-                const int e = b + u * G + gl;
-                acc[u] = test(min(e, c.y - 1), c.x) && e < c.y && c.z + e != i;
+                const int e = b + u * G + gl, ec = min(e, n - 1);
+                g[u] = cand_glob(c, na, ec);
+                acc[u] = test(cand_at<FROM_LDS>(c, na, ec)) && e < n && g[u] != i;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const unsigned long long m = __ballot(acc[u]) & gmask;
                 if (acc[u]) {
                     const int k2 = cnt + __popcll(m & below);
-                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = c.z + b + u * G + gl;
+                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = g[u];
                 }
                 cnt += __popcll(m);
             }
@@ -539,18 +578,25 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
     // candidate of the last visited cell, else (rare) of any staged cell
     if (cnt & 7) {
         int pad = -1;
-        const int4 cl = T.pk[last_cell];
-        for (int b = 0; b < cl.y; b += G) {
-            const int e = b + gl;
-            const bool r = e < cl.y && !test(e, cl.x) && cl.z + e != i;
-            const unsigned long long m = __ballot(r) & gmask;
-            if (m) { pad = cl.z + b + (__ffsll(m) - 1) - (__ffsll(gmask) - 1); break; }
+        {
+            const int4 cl = T.pk[last_cell];
+            const int na = T.na[last_cell];
+            for (int b = 0; b < cl.y; b += G) {
+                const int e = b + gl;
+                const int g = cand_glob(cl, na, min(e, cl.y - 1));
+                const bool r = e < cl.y && !test(cand_at<FROM_LDS>(cl, na, min(e, cl.y - 1))) && g != i;
+                const unsigned long long m = __ballot(r) & gmask;
+                if (m) { pad = cand_glob(cl, na, b + (__ffsll(m) - 1) - (__ffsll(gmask) - 1)); break; }
+            }
         }
         if (gl == 0) {
-            for (int k = 0; k < (nd == 1 ? 1 : 9 * NX) && pad < 0; ++k) {
-                const int st = T.start[k], n = T.cnt[k], g0 = T.glob[k];
-                for (int e = 0; e < n && pad < 0; ++e)
-                    if (!test(e, st) && g0 + e != i) pad = g0 + e;
+            for (int k = 0; k < T.ncell && pad < 0; ++k) {
+                const int4 c = T.pk[k];
+                const int na = T.na[k];
+                for (int e = 0; e < c.y && pad < 0; ++e) {
+                    const int g = cand_glob(c, na, e);
+                    if (!test(cand_at<FROM_LDS>(c, na, e)) && g != i) pad = g;
+                }
             }
             if (pad < 0) atomicOr(a.status + s, 8);
             for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
@@ -592,24 +638,26 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
     for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 4,
               remap_block(blockIdx.x, gridDim.x, a.xcd), gridDim.x, [&](int s, int item) {
         const RepDev rp = a.rep[s];
-        const int nd = rp.nd;
+        const int nd = rp.nd, planes = rp.planes, nc = nd * nd * nd;
         const int *cs = a.cs_new + rp.coff;
-        int m0, m1, NX = 1, x0 = 0, x1 = 1, rowbase = 0;
+        // members: the segment's slots of plane 0 ([sm0, sm0 + ms0)), then
+        // those of plane 1; this item builds member indices [m0, m1)
+        int m0, m1, sm0, ms0, sm1, NX = 1;
         bool full = true;
         if (nd == 1) {
-            m0 = rp.off + item * a.single_members;
-            m1 = min(m0 + a.single_members, rp.off + rp.n);
+            sm0 = rp.off; ms0 = rp.n; sm1 = rp.off + rp.n; // the planes are adjacent slots
+            m0 = item * a.single_members;
+            m1 = min(m0 + a.single_members, rp.n);
             if (t == 0) {
-                T.glob[0] = rp.off;
-                T.cnt[0] = rp.n;
-                T.start[0] = 0;
-                T.run_lds[0] = 0; T.run_glob[0] = rp.off; T.run_lds[1] = rp.n;
-                T.nruns = 1;
+                const int na = cs[1] - cs[0];
+                T.pk[0] = make_int4(0, rp.n, cs[0], planes > 1 ? cs[1] : cs[0] + na);
+                T.na[0] = na;
+                T.ncell = 1;
+                T.NX = 1;
                 T.total = rp.n;
                 T.fits = rp.n <= a.lds_cap;
-                if (!T.fits) T.start[0] = rp.off;
-                T.NX = 1;
-                if (item == 0 && a.from_scratch) { a.cs[rp.coff] = cs[0]; a.cs[rp.coff + 1] = cs[1]; }
+                if (item == 0 && a.from_scratch)
+                    for (int k = 0; k <= planes; ++k) a.cs[rp.coff + k] = cs[k];
             }
         } else {
             const int W = a.width;
@@ -618,19 +666,21 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             const int part = item % rp.bparts, segitem = item / rp.bparts;
             const int seg = segitem % nseg, row = segitem / nseg;
             const int cy = row % nd, cz = row / nd;
-            x0 = full ? 0 : (seg * nd) / nseg;           // balanced segments
-            x1 = full ? nd : ((seg + 1) * nd) / nseg;
+            const int x0 = full ? 0 : (seg * nd) / nseg; // balanced segments
+            const int x1 = full ? nd : ((seg + 1) * nd) / nseg;
             NX = full ? nd : x1 - x0 + 2;
-            rowbase = nd * (cy + nd * cz);
-            {   // this item's share of the segment's members
-                const int s0 = cs[rowbase + x0], ms = cs[rowbase + x1] - s0;
-                m0 = s0 + (int)(((long long)part * ms) / rp.bparts);
-                m1 = s0 + (int)(((long long)(part + 1) * ms) / rp.bparts);
-            }
+            const int rowbase = nd * (cy + nd * cz);
+            sm0 = cs[rowbase + x0];
+            ms0 = cs[rowbase + x1] - sm0;
+            sm1 = planes > 1 ? cs[nc + rowbase + x0] : 0;
+            const int ms = ms0 + (planes > 1 ? cs[nc + rowbase + x1] - sm1 : 0);
+            // this item's share of the segment's members
+            m0 = (int)(((long long)part * ms) / rp.bparts);
+            m1 = (int)(((long long)(part + 1) * ms) / rp.bparts);
             if (a.from_scratch && part == 0) { // retire the old cell starts of this segment
-                for (int k = x0 + t; k < x1; k += B) a.cs[rp.coff + rowbase + k] = cs[rowbase + k];
-                if (t == 0 && rowbase + x1 == nd * nd * nd)
-                    a.cs[rp.coff + nd * nd * nd] = cs[nd * nd * nd];
+                for (int pl = 0; pl < planes; ++pl)
+                    for (int k = x0 + t; k < x1; k += B) a.cs[rp.coff + pl * nc + rowbase + k] = cs[pl * nc + rowbase + k];
+                if (t == 0 && rowbase + x1 == nc) a.cs[rp.coff + planes * nc] = cs[planes * nc];
             }
             const int gs = full ? 0 : (x0 - 1 + nd) % nd; // first staged x
             for (int k = t; k < 9 * NX; k += B) {
@@ -642,51 +692,44 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
                 gy += gy < 0 ? nd : 0; gy -= gy >= nd ? nd : 0;
                 gz += gz < 0 ? nd : 0; gz -= gz >= nd ? nd : 0;
                 const int cc = gx + nd * (gy + nd * gz);
-                T.glob[k] = cs[cc];
-                T.cnt[k] = cs[cc + 1] - cs[cc];
+                const int ga = cs[cc], na = cs[cc + 1] - ga;
+                const int gb = planes > 1 ? cs[nc + cc] : ga + na;
+                const int nb = planes > 1 ? cs[nc + cc + 1] - gb : 0;
+                T.pk[k] = make_int4(0, na + nb, ga, gb);
+                T.na[k] = na;
             }
-            if (t == 0) T.NX = NX;
+            if (t == 0) { T.NX = NX; T.ncell = 9 * NX; }
             __syncthreads();
             if (t < 64) { // exclusive scan of the staged cell sizes (one wave)
                 const int ncells = 9 * NX;
                 int carry = 0;
                 for (int b = 0; b < ncells; b += 64) {
                     const int k = b + t;
-                    const int v = k < ncells ? T.cnt[k] : 0;
+                    const int v = k < ncells ? T.pk[k].y : 0;
                     int incl = v;
 #pragma unroll
                     for (int o = 1; o < 64; o <<= 1) {
                         const int u = __shfl_up(incl, o, 64);
                         if (t >= o) incl += u;
                     }
-                    if (k < ncells) T.start[k] = carry + incl - v;
+                    if (k < ncells) T.pk[k].x = carry + incl - v;
                     carry += __shfl(incl, 63, 64);
                 }
                 if (t == 0) { T.total = carry; T.fits = carry <= a.lds_cap; }
             }
-            __syncthreads();
-            if (t < 9) { // contiguous global runs of each staged row (<= 2 with wrap)
-                const int lenA = full ? NX : min(NX, nd - gs);
-                const int k0 = t * NX;
-                T.run_lds[2 * t] = T.start[k0];
-                T.run_glob[2 * t] = T.glob[k0];
-                T.run_lds[2 * t + 1] = lenA < NX ? T.start[k0 + lenA] : T.start[k0 + NX - 1] + T.cnt[k0 + NX - 1];
-                T.run_glob[2 * t + 1] = lenA < NX ? T.glob[k0 + lenA] : T.glob[k0 + NX - 1] + T.cnt[k0 + NX - 1];
-                if (t == 8) { T.run_lds[18] = T.total; T.nruns = 18; }
-            }
-            __syncthreads();
-            if (!T.fits) // candidates are read from the arena: start = global index
-                for (int k = t; k < 9 * NX; k += B) T.start[k] = T.glob[k];
         }
         __syncthreads();
-        for (int k = t; k < (nd == 1 ? 1 : 9 * NX); k += B) T.pk[k] = make_int4(T.start[k], T.cnt[k], T.glob[k], 0);
         const bool fits = T.fits != 0;
-        if (fits) { // stage: element e lies in the last run whose LDS start is <= e
-            const int tot = T.total, nr = T.nruns;
-            int r = 0; // only moves forward as e grows
+        if (fits) { // stage: element e belongs to the last cell whose LDS start is <= e
+            const int tot = T.total, ncl = T.ncell;
             for (int e = t; e < tot; e += B) {
-                while (r + 1 < nr && T.run_lds[r + 1] <= e) ++r;
-                const int g = T.run_glob[r] + (e - T.run_lds[r]);
+                int lo = 0, hi = ncl;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (T.pk[mid].x <= e) lo = mid; else hi = mid;
+                }
+                const int4 c = T.pk[lo];
+                const int g = cand_glob(c, T.na[lo], e - c.x);
                 if (NS == 2) {
                     cand[2 * e] = a.src_x[g];
                     cand[2 * e + 1] = a.src_x[(size_t)a.A.P + g];
@@ -694,12 +737,15 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             }
         }
         __syncthreads();
-        // the member's cell: own-row staged cell whose range holds i
-        auto member_cell = [&](int i) {
+        // member index -> slot, and the member's own-row staged cell (the
+        // last one whose start in the member's plane is <= i)
+        auto slot_of = [&](int k) { return k < ms0 ? sm0 + k : sm1 + (k - ms0); };
+        auto member_cell = [&](int i, int k) {
             if (nd == 1) return 0;
+            const bool b = k >= ms0;
             int lx = full ? 0 : 1;
             const int le = full ? NX - 1 : NX - 2;
-            while (lx < le && T.glob[4 * NX + lx + 1] <= i) ++lx;
+            while (lx < le && (b ? T.pk[4 * NX + lx + 1].w : T.pk[4 * NX + lx + 1].z) <= i) ++lx;
             return lx;
         };
         // lanes per member: the replica's (fixed by the launch, or one lane
@@ -711,8 +757,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             while (G < 64 && (2 * G) * (m1 - m0) <= B) G *= 2;
         }
         if (G == 1) {
-            for (int i = m0 + t; i < m1; i += B) {
-                const int lx_m = member_cell(i);
+            for (int k = m0 + t; k < m1; k += B) {
+                const int i = slot_of(k), lx_m = member_cell(i, k);
                 if (fits) build_member<P, true>(a, rp, i, lx_m, T, full, cand, s, nd);
                 else build_member<P, false>(a, rp, i, lx_m, T, full, cand, s, nd);
                 copy_back<P>(a, i);
@@ -722,8 +768,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             const unsigned long long gmask =
                 G == 64 ? ~0ull : ((1ull << G) - 1ull) << (lane & ~(G - 1));
             const unsigned long long below = (1ull << lane) - 1ull;
-            for (int i = m0 + t / G; i < m1; i += B / G) {
-                const int lx_m = member_cell(i);
+            for (int k = m0 + t / G; k < m1; k += B / G) {
+                const int i = slot_of(k), lx_m = member_cell(i, k);
                 if (fits) build_member_grp<P, true>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
                 else build_member_grp<P, false>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
                 if (gl == 0) copy_back<P>(a, i);
@@ -746,7 +792,7 @@ hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s)
 
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan, dim3(a.max_slots), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(a.max_slots), dim3(SCAN_B), 0, s, a);
     LAUNCH_CHECK();
 }
 

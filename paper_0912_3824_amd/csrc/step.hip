@@ -286,7 +286,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
     rc2[0] = pp.rc2d[si * 2]; rc2[1] = pp.rc2d[si * 2 + 1];
     sig2[0] = pp.sig2d[si * 2]; sig2[1] = pp.sig2d[si * 2 + 1];
     e24[0] = pp.eps24d[si * 2]; e24[1] = pp.eps24d[si * 2 + 1];
-    const int nq = ((cnt + 7) >> 3) << 1;
+    const int nq = (cnt + 3) >> 2; // blocks of four (a partial block is completed by padding)
     for (int q = sub; q < nq; q += lpp) {
         const int4 jj = list_row(A, i, q);
         const int js[4] = {jj.x, jj.y, jj.z, jj.w};
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         else bad = !isfinite(st.x + st.y + st.z);
         cell = rp.nd == 1 ? 0 : fixed_cell(X.x, X.y, X.z, rp.nd);
     }
-    atomicAdd(a.count_cur + rp.coff + cell, 1);
+    atomicAdd(a.count_cur + rp.coff + sort_key(cell, meta, rp.planes, rp.nd), 1);
     if (far && atomicOr(a.need_cur + r, 1) == 0) { // first to flag: enlist the slot
         const int k = atomicAdd(a.rlist_cur, 1);
         a.rlist_cur[1 + k] = r;

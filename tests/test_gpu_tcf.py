@@ -30,7 +30,7 @@ def _free_gas(n=216, spacing=10.0, seed=4):
 def test_ballistic_correlations(prec):
     s = _free_gas()
     every, M, levels, block = 4, 130, 3, 5
-    pool = pool_for([s], prec, max_cells=10000)  # a dilute box: 21^3 cells
+    pool = pool_for([s], prec, max_cells=20000)  # a dilute box: 21^3 cells per species plane
     t = pool.tcf(0, levels, block, q=7.25)
     for m in range(M):
         if m:
@@ -98,7 +98,7 @@ def test_interacting_correlations_match_oracle(prec):
 def test_sampling_a_detached_replica_is_an_error():
     from paper_0912_3824_amd import mdx
     s = _free_gas()
-    pool = pool_for([s], "ds", max_slots=2, max_cells=10000)
+    pool = pool_for([s], "ds", max_slots=2, max_cells=20000)
     t = pool.tcf(0, 2, 4, q=1.0)
     t.sample()
     pool.detach(0)

@@ -53,10 +53,12 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def read_traffic(workload: str, prec: str, n_particles: int):
+def read_traffic(workload: str, prec: str, n_particles: int, cell_order: str = "row"):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{prec}_{workload}_pmc.json")
+    counter summary, if it was taken on the current kernel source and in the
+    same cell order."""
+    tag = "" if cell_order == "row" else f"_{cell_order}"
+    path = os.path.join(ROOT, "profiles", f"k_step_{prec}_{workload}{tag}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -135,6 +137,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=20240101)
+    ap.add_argument("--cell-order", default="row", choices=["row", "morton", "hilbert"],
+                    help="order of the cells in the particle sort")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -153,7 +157,7 @@ def main():
     n_total = sum(s.n for s in systems)
     log(f"workload {args.workload}: {len(systems)} replica(s), {n_total} particles, precision {prec}")
 
-    pool = mdx.md_init(systems, prec)
+    pool = mdx.md_init(systems, prec, cell_order=args.cell_order)
     from paper_0912_3824_amd import tune
     tuned = tune.apply_cached(pool)  # launch shapes from the autotuner, if tuned
     pool.set_launch(graph_steps=args.graph_steps)
@@ -217,7 +221,7 @@ def main():
     roof["algorithmic_ops_per_launch"] = int(ops_launch)
     roof["hbm_frac"] = round(hbm_gbs / HBM_PEAK_GBS, 4)
     roof["alu_frac"] = round(alu_tops / VALU_PEAK_TOPS, 4)
-    traffic = read_traffic(args.workload, prec, n_total)
+    traffic = read_traffic(args.workload, prec, n_total, args.cell_order)
     roof["traffic"] = traffic
     log(f"roofline: {roof}")
 
@@ -242,6 +246,7 @@ def main():
         "data": "synthetic (seeded fcc-subset start, Maxwell-Boltzmann velocities, rescaled equilibration)",
         "config": {"workload": args.workload, "description": desc, "particles": n_total,
                    "replicas": len(systems), "precision": prec, "skin": systems[0].skin,
+                   "cell_order": args.cell_order,
                    "graph_steps": args.graph_steps, "equil_steps": args.equil,
                    "launch": pool.get_launch(),
                    "mean_list_entries": round(mean_list, 3), "rebuilds_in_timed_region": int(rebuilds)},

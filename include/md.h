@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 2
+#define MD_ABI_VERSION 3
 
 typedef struct md_system md_system;
 
@@ -74,6 +74,18 @@ typedef enum {
     MD_MIXED64 = 2, /* FP32 pair force, FP64 force sum, FP64 velocity Verlet */
     MD_FP64 = 3     /* everything in FP64 */
 } md_precision;
+
+/* Order of the cells in the particle sort.  Sec. 2.2 reorders particles
+ * along a Hilbert curve for the locality of neighbour reads; here the sort
+ * is by cell (each species separately), and the cells follow one of these
+ * orders.  For nd^3 cells, the Morton and Hilbert orders are those of the
+ * enclosing 2^b grid with the cells outside nd^3 skipped. */
+typedef enum {
+    MD_ORDER_ROW = 0,     /* rank = x + nd (y + nd z) */
+    MD_ORDER_MORTON = 1,  /* Z-order: coordinate bits interleaved (x lowest) */
+    MD_ORDER_HILBERT = 2  /* Hilbert curve (Skilling's transposed index):
+                             consecutive cells are face neighbours on 2^b grids */
+} md_cell_order_kind;
 
 /* Per-replica status bits (sticky until md_detach / md_restore). */
 #define MD_ST_LIST_OVERFLOW 1 /* a particle had more neighbours than nbr_capacity */
@@ -109,7 +121,9 @@ typedef struct {
                                    sum is split into this many partial sums,
                                    combined in a fixed order, so results are
                                    bitwise reproducible for a given value. */
-    int32_t reserved;
+    int32_t cell_order;    /* md_cell_order_kind: the order of the cells in the particle
+                              sort (Sec. 2.2 orders particles along a Hilbert curve);
+                              part of the arithmetic (it fixes the list order) */
     double smooth;         /* h of the C2 smoothing of Sec. 4: the truncated-and-
                               shifted potential times g(x) = x^4 / (1 + x^4),
                               x = (r - rc_ab) / (h sigma_ab); 0 = no smoothing;
@@ -361,6 +375,12 @@ const char *md_strerror(md_status st);
 /* Last error text of a handle ("" if none); valid until the next call. */
 const char *md_last_error(const md_system *sys);
 int32_t md_abi_version(void);
+
+/* Host-only: rank[c] (c = x + nd (y + nd z), nd^3 entries, caller-owned) of
+ * every cell of an nd^3 grid in the cell order `order` (md_cell_order_kind),
+ * the table the library uses for replicas with nd cells per edge.  Touches
+ * no device.  Errors: MD_E_ARG (nd outside 1..1024, bad order, null rank). */
+md_status md_cell_order(int32_t nd, int32_t order, int32_t *rank);
 
 #ifdef __cplusplus
 }

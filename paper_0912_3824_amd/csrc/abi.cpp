@@ -95,6 +95,7 @@ struct md_system {
     int *nbr = nullptr, *nbr_cnt = nullptr;
     double *obs = nullptr, *obs_out = nullptr;
     int *count[2]{}, *cs = nullptr, *cs_new = nullptr;
+    int *corder = nullptr; // per-replica cell rank tables (cell arena offsets)
     RepDev *rep = nullptr;
     Ctl *ctl[2]{};
     int *target = nullptr, *need[2]{}, *rlist[2]{}, *status = nullptr, *nreb = nullptr;
@@ -181,6 +182,8 @@ static md_status validate_cfg(const md_config *c, std::string *why)
         c->lanes_per_particle != 4)
         return bad("lanes_per_particle must be 0, 1, 2 or 4");
     if (!(c->smooth >= 0) || !std::isfinite(c->smooth)) return bad("smooth must be >= 0 and finite");
+    if (c->cell_order != MD_ORDER_ROW && c->cell_order != MD_ORDER_MORTON && c->cell_order != MD_ORDER_HILBERT)
+        return bad("cell_order must be MD_ORDER_ROW, MD_ORDER_MORTON or MD_ORDER_HILBERT");
     return MD_OK;
 }
 
@@ -235,6 +238,7 @@ static int64_t carve(md_system *s, const Layout &L, char *base)
     d->count[1] = c.take<int>(L.cells);
     d->cs = c.take<int>(L.cells);
     d->cs_new = c.take<int>(L.cells);
+    d->corder = c.take<int>(L.cells);
     d->rep = c.take<RepDev>(L.slots);
     d->ctl[0] = c.take<Ctl>(L.slots);
     d->ctl[1] = c.take<Ctl>(L.slots);
@@ -440,6 +444,7 @@ static StepArgs step_args(const md_system *s, int p)
     a.rlist_other = s->rlist[p ^ 1];
     a.count_cur = s->count[p];
     a.count_other = s->count[p ^ 1];
+    a.corder = s->corder;
     a.status = s->status;
     a.obs = s->obs;
     a.pp = s->pp;
@@ -477,6 +482,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     pa.ctl = s->ctl[p ^ 1];
     pa.cs = s->cs;
     pa.cs_new = s->cs_new;
+    pa.corder = s->corder;
     pa.snap = s->snap[p ^ 1];
     for (int k = 0; k < 3; ++k) pa.sc_st[k] = s->sc_st[k];
     pa.sc_snap = s->sc_snap;
@@ -501,6 +507,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     ba.ctl = s->ctl[p ^ 1];
     ba.cs = s->cs;
     ba.cs_new = s->cs_new;
+    ba.corder = s->corder;
     ba.src_x = s->sc_snap;
     ba.snap_cur = s->snap[p ^ 1];
     for (int k = 0; k < 3; ++k) ba.sc_st[k] = s->sc_st[k];
@@ -531,6 +538,7 @@ static md_status launch_build_main(md_system *s, int slot)
     ba.ctl = s->ctl[0];
     ba.cs = s->cs;
     ba.cs_new = s->cs_new;
+    ba.corder = s->corder;
     ba.src_x = s->xref;
     ba.snap_cur = s->snap[0];
     ba.status = s->status;
@@ -622,6 +630,77 @@ static void get_f4(const uint4 &u, float &a, float &b, float &c, float &d)
     memcpy(&a, &u.x, 4); memcpy(&b, &u.y, 4); memcpy(&c, &u.z, 4); memcpy(&d, &u.w, 4);
 }
 
+// ------------------------------------------------------------ cell order
+// Keys of cell (x, y, z) on a 2^bits grid.  Morton: the coordinates' bits
+// interleaved (x lowest).  Hilbert: Skilling's method (J. Skilling,
+// "Programming the Hilbert curve", AIP Conf. Proc. 707, 381 (2004)) turns
+// the coordinates into the transposed Hilbert index, whose bits, read level
+// by level from the top, give the position along the curve; consecutive
+// positions are face-adjacent cells.
+static uint64_t morton_key(uint32_t x, uint32_t y, uint32_t z, int bits)
+{
+    uint64_t k = 0;
+    for (int l = bits - 1; l >= 0; --l)
+        k = (k << 3) | ((uint64_t)((z >> l) & 1u) << 2) | ((uint64_t)((y >> l) & 1u) << 1) | ((x >> l) & 1u);
+    return k;
+}
+
+static uint64_t hilbert_key(uint32_t x, uint32_t y, uint32_t z, int bits)
+{
+    uint32_t X[3] = {x, y, z};
+    const uint32_t top = 1u << (bits - 1);
+    for (uint32_t q = top; q > 1; q >>= 1) { // undo the excess work of the curve's reflections
+        const uint32_t low = q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & q) {
+                X[0] ^= low; // invert the low bits of the first axis
+            } else { // exchange the low bits of the first axis and axis i
+                const uint32_t t = (X[0] ^ X[i]) & low;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1]; // Gray encode
+    uint32_t t = 0;
+    for (uint32_t q = top; q > 1; q >>= 1)
+        if (X[2] & q) t ^= q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t k = 0;
+    for (int l = bits - 1; l >= 0; --l)
+        for (int i = 0; i < 3; ++i) k = (k << 1) | ((X[i] >> l) & 1u);
+    return k;
+}
+
+// rank[c] of each cell c = x + nd (y + nd z) of an nd^3 grid in the order
+// `order`: row-major (rank = c), or along the Morton or Hilbert curve of the
+// enclosing 2^bits grid (cells outside the nd^3 grid are skipped).
+static void cell_ranks(int nd, int order, int *rank)
+{
+    const int64_t nc = (int64_t)nd * nd * nd;
+    if (order == MD_ORDER_ROW || nd == 1) {
+        for (int64_t c = 0; c < nc; ++c) rank[c] = (int)c;
+        return;
+    }
+    int bits = 1;
+    while ((1 << bits) < nd) ++bits;
+    std::vector<std::pair<uint64_t, int>> key(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        const uint32_t x = (uint32_t)(c % nd), y = (uint32_t)((c / nd) % nd), z = (uint32_t)(c / ((int64_t)nd * nd));
+        key[c] = {order == MD_ORDER_MORTON ? morton_key(x, y, z, bits) : hilbert_key(x, y, z, bits), (int)c};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t r = 0; r < nc; ++r) rank[key[r].second] = (int)r;
+}
+
+// The replica's cell rank table (used when RepDev::curve is set).
+static std::vector<int> ranks_of(const md_system *s, const SlotHost &h)
+{
+    std::vector<int> rk((size_t)h.nd * h.nd * h.nd);
+    cell_ranks(h.nd, s->cfg.cell_order, rk.data());
+    return rk;
+}
+
 static RepDev repdev_of(const md_system *s, const SlotHost &h)
 {
     RepDev r;
@@ -631,6 +710,7 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     r.nd = h.nd;
     r.coff = (int)h.coff;
     r.planes = s->cfg.n_species;
+    r.curve = s->cfg.cell_order != MD_ORDER_ROW && h.nd > 1;
     r.L = h.L;
     r.invL = 1.0 / h.L;
     r.fxs = 4294967296.0 / h.L;
@@ -733,6 +813,8 @@ static md_status upload_slot(md_system *s, int slot, const SlotHost &h, const Ho
     HIPCHK(s, hipMemcpyAsync(s->cs + h.coff, hr.cs.data(), 4 * hr.cs.size(), hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->cs_new + h.coff, hr.cs.data(), 4 * hr.cs.size(), hipMemcpyHostToDevice, st));
     RepDev r = repdev_of(s, h);
+    const std::vector<int> rk = ranks_of(s, h); // kept until the stream synchronises below
+    if (r.curve) HIPCHK(s, hipMemcpyAsync(s->corder + h.coff, rk.data(), 4 * rk.size(), hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->rep + slot, &r, sizeof r, hipMemcpyHostToDevice, st));
     for (int p = 0; p < 2; ++p) {
         HIPCHK(s, hipMemcpyAsync(s->ctl[p] + slot, &c, sizeof c, hipMemcpyHostToDevice, st));
@@ -796,6 +878,14 @@ static md_status finish_attach(md_system *s, int slot)
 extern "C" {
 
 int32_t md_abi_version(void) { return MD_ABI_VERSION; }
+
+md_status md_cell_order(int32_t nd, int32_t order, int32_t *rank)
+{
+    if (nd < 1 || nd > 1024 || !rank) return MD_E_ARG;
+    if (order != MD_ORDER_ROW && order != MD_ORDER_MORTON && order != MD_ORDER_HILBERT) return MD_E_ARG;
+    cell_ranks(nd, order, rank);
+    return MD_OK;
+}
 
 const char *md_strerror(md_status st)
 {
@@ -920,6 +1010,7 @@ md_status md_attach(md_system *s, int32_t slot, const md_replica *rep, const int
     SlotHost h;
     if ((st = alloc_slot_ranges(s, slot, n, rep->box, h)) != MD_OK) return st;
     RepDev r = repdev_of(s, h);
+    const std::vector<int> rank = ranks_of(s, h);
     const int NW = s->lay.NW, NS = s->lay.NS;
     std::vector<uint4> w(3 * (size_t)n), sn(2 * (size_t)n);
     std::vector<int4> mt(n);
@@ -939,7 +1030,7 @@ md_status md_attach(md_system *s, int32_t slot, const md_replica *rep, const int
         uint32_t m = meta_word(slot, species ? species[k] : 0);
         encode_particle(s, r, x, v, img, m, &w[3 * (size_t)k], &sn[2 * (size_t)k]);
         mt[k] = make_int4(img[0], img[1], img[2], k);
-        cell[k] = sort_key(cell_of_snap(s, r, &sn[2 * (size_t)k]), m, r.planes, r.nd);
+        cell[k] = sort_key(rank[cell_of_snap(s, r, &sn[2 * (size_t)k])], m, r.planes, r.nd);
     }
     // stable counting sort by species plane and cell
     const int ncell = r.planes * h.nd * h.nd * h.nd;
@@ -1024,6 +1115,7 @@ md_status md_rebuild_neighbours(md_system *s)
     ca.rep = s->rep;
     ca.ctl = s->ctl[p];
     ca.count = s->count[kp];
+    ca.corder = s->corder;
     HIPCHK(s, launch_count(s->prec, ca, s->stream));
     // the rebuild kernels of a step of parity kp read snap[kp ^ 1] == snap[p]
     return launch_rebuild(s, kp, -2, true);
@@ -1437,6 +1529,7 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
     if ((st = alloc_slot_ranges(s, slot, (int)n, H.L, h)) != MD_OK) return st;
     if (h.nd != H.nd) { release_slot_ranges(s, h); return fail(s, MD_E_ARG, "cell grid mismatch"); }
     RepDev r = repdev_of(s, h);
+    const std::vector<int> rank = ranks_of(s, h);
     const char *b = (const char *)blob + sizeof H;
     HostRep hr;
     for (int q = 0; q < H.NW; ++q) { hr.st[q].resize(n); memcpy(hr.st[q].data(), b, 16 * n); b += 16 * n; }
@@ -1467,7 +1560,7 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
             get_dbl2(sn[1], z, w);
             mw = meta_of_bits(w);
         }
-        int c = sort_key(cell_of_snap(s, r, sn), mw, r.planes, r.nd);
+        int c = sort_key(rank[cell_of_snap(s, r, sn)], mw, r.planes, r.nd);
         if (c < prev) { release_slot_ranges(s, h); return fail(s, MD_E_ARG, "checkpoint order is not by cell"); }
         prev = c;
         hr.cs[c + 1]++;

@@ -54,6 +54,14 @@ __device__ __forceinline__ int remap_block(int b, int nblk, int on)
 
 __device__ __forceinline__ int slot_of_meta(uint32_t w) { return (int)(w >> SLOT_SHIFT); }
 
+// Rank of cell c (= x + nd (y + nd z)) in the replica's cell order: itself
+// in row-major order, else from the replica's rank table (a space-filling
+// curve through the cells).
+__device__ __forceinline__ int cell_rank(int c, const RepDev &r, const int *corder)
+{
+    return r.curve ? corder[r.coff + c] : c;
+}
+
 __device__ __forceinline__ int find_item_slot(const int *pref, int nslots, int item)
 {
     // pref[0..nslots] non-decreasing; find s with pref[s] <= item < pref[s+1]

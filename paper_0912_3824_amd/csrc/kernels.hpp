@@ -29,6 +29,7 @@ struct StepArgs {
     int *need_cur, *need_other;
     int *rlist_cur, *rlist_other; // [0] = count, [1..] = slots that must rebuild
     int *count_cur, *count_other;
+    const int *corder; // per-replica cell rank tables (cell arena offsets)
     int *status;
     double *obs;
     PairDev pp;
@@ -41,6 +42,7 @@ struct CountArgs {
     const RepDev *rep;
     const Ctl *ctl;
     int *count;
+    const int *corder;
 };
 
 struct ScanArgs {
@@ -64,6 +66,7 @@ struct PermArgs {
     const int *rlist;
     const Ctl *ctl;
     const int *cs, *cs_new;
+    const int *corder;
     const uint4 *snap;
     uint4 *sc_st[3];
     uint4 *sc_snap;
@@ -82,6 +85,7 @@ struct BuildArgs {
     const Ctl *ctl;
     int *cs;
     const int *cs_new;
+    const int *corder;
     const uint4 *src_x;
     uint4 *snap_cur;
     const uint4 *sc_st[3];

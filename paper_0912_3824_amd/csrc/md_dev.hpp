@@ -38,6 +38,7 @@ struct RepDev {
     int nd;       // cells per box edge (1 = single-cell mode)
     int coff;     // first cell in the cell arena (planes * nd^3 + 1 entries reserved)
     int planes;   // species planes of the sort key (1, or 2 for a binary mixture)
+    int curve;    // 1: cells are ranked along a space-filling curve (rank table at coff)
     double L;     // box edge
     double invL;  // 1 / L
     double fxs;   // 2^32 / L   (double -> fixed point)
@@ -139,13 +140,14 @@ __host__ __device__ __forceinline__ int dbl_cell1(double x, double L, double inv
     return c;
 }
 
-// Sort key of a particle (its index in the replica's cell arrays): the cell
-// within the plane of its species.  With two planes every species is sorted
-// by cell on its own (all A, then all B), so a wave of the force kernel
-// holds particles of one species, whose lists are of similar length.
-__host__ __device__ __forceinline__ int sort_key(int cell, uint32_t meta, int planes, int nd)
+// Sort key of a particle (its index in the replica's cell arrays): the rank
+// of its cell in the replica's cell order, within the plane of its species.
+// With two planes every species is sorted by cell on its own (all A, then
+// all B), so a wave of the force kernel holds particles of one species,
+// whose lists are of similar length.
+__host__ __device__ __forceinline__ int sort_key(int rank, uint32_t meta, int planes, int nd)
 {
-    return planes > 1 ? (int)(meta & SPECIES_MASK) * nd * nd * nd + cell : cell;
+    return planes > 1 ? (int)(meta & SPECIES_MASK) * nd * nd * nd + rank : rank;
 }
 
 __host__ __device__ __forceinline__ int dbl_cell(double x, double y, double z, double L, double invL, int nd)

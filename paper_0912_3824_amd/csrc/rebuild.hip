@@ -26,7 +26,7 @@ __global__ void k_count(const CountArgs a)
     int cell;
     if (NS == 2) cell = dbl_cell(x, y, z, rp.L, rp.invL, rp.nd);
     else cell = rp.nd == 1 ? 0 : fixed_cell(s0.x, s0.y, s0.z, rp.nd);
-    atomicAdd(a.count + rp.coff + sort_key(cell, meta, rp.planes, rp.nd), 1);
+    atomicAdd(a.count + rp.coff + sort_key(cell_rank(cell, rp, a.corder), meta, rp.planes, rp.nd), 1);
 }
 
 // ------------------------------------------------------------ k_scan
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6;
-    __shared__ int pref[4][55], pst[4][54];
+    __shared__ int pref[4][55], pst[4][54], srt[4][27];
     for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 3,
               blockIdx.x * wpb + wv, gridDim.x * wpb, [&](int s, int c) {
         const RepDev rp = a.rep[s];
@@ -222,33 +222,33 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
         const int *cs = a.cs + rp.coff;
         // new cell c of every plane: plane-0 members go to [dst0, dst0 +
         // want0), plane-1 members to [dst1, dst1 + want1)
-        const int dst0 = a.cs_new[rp.coff + c], want0 = a.cs_new[rp.coff + c + 1] - dst0;
-        const int dst1 = planes > 1 ? a.cs_new[rp.coff + nc + c] : 0;
-        const int want1 = planes > 1 ? a.cs_new[rp.coff + nc + c + 1] - dst1 : 0;
-        // the old cells that can hold members of new cell c: plane 0's in
-        // ascending order, then plane 1's (so that the flattened candidates
+        const int rc = cell_rank(c, rp, a.corder);
+        const int dst0 = a.cs_new[rp.coff + rc], want0 = a.cs_new[rp.coff + rc + 1] - dst0;
+        const int dst1 = planes > 1 ? a.cs_new[rp.coff + nc + rc] : 0;
+        const int want1 = planes > 1 ? a.cs_new[rp.coff + nc + rc + 1] - dst1 : 0;
+        // the old cells that can hold members of new cell c, in ascending
+        // rank: plane 0's, then plane 1's (so that the flattened candidates
         // are in old slot order); one range per lane
         const int nold = nd == 1 ? 1 : 27, nr = planes * nold;
+        if (nd > 1) { // rank the 27 neighbour cells (distinct for nd >= 3)
+            int orank = 0x7fffffff;
+            if (lane < 27) {
+                const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
+                int ox = cx + lane % 3 - 1, oy = cy + (lane / 3) % 3 - 1, oz = cz + lane / 9 - 1;
+                ox += ox < 0 ? nd : 0; ox -= ox >= nd ? nd : 0;
+                oy += oy < 0 ? nd : 0; oy -= oy >= nd ? nd : 0;
+                oz += oz < 0 ? nd : 0; oz -= oz >= nd ? nd : 0;
+                orank = cell_rank(ox + nd * (oy + nd * oz), rp, a.corder);
+            }
+            int pos = 0;
+            for (int l = 0; l < 27; ++l) pos += __shfl(orank, l, 64) < orank;
+            if (lane < 27) srt[wv][pos] = orank;
+            __builtin_amdgcn_wave_barrier();
+        }
         int len = 0, st0 = 0;
         if (lane < nr) {
             const int pl = lane >= nold, kk = lane - pl * nold;
-            int oc = 0;
-            if (nd > 1) {
-                const int cx = c % nd, cy = (c / nd) % nd, cz = c / (nd * nd);
-                int v[3][3] = {{(cx + nd - 1) % nd, cx, (cx + 1) % nd},
-                               {(cy + nd - 1) % nd, cy, (cy + 1) % nd},
-                               {(cz + nd - 1) % nd, cz, (cz + 1) % nd}};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int *u = v[d];
-                    if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
-                    if (u[1] > u[2]) { int t = u[1]; u[1] = u[2]; u[2] = t; }
-                    if (u[0] > u[1]) { int t = u[0]; u[0] = u[1]; u[1] = t; }
-                }
-                const int kx = kk % 3, ky = (kk / 3) % 3, kz = kk / 9;
-                oc = v[0][kx] + nd * (v[1][ky] + nd * v[2][kz]);
-            }
-            oc += pl * nc;
+            const int oc = pl * nc + (nd > 1 ? srt[wv][kk] : 0);
             st0 = cs[oc];
             len = cs[oc + 1] - st0;
         }
@@ -318,7 +318,8 @@ struct BuildTabs {
     // both planes, global start in plane 0, global start in plane 1)
     int4 pk[BUILD_TAB];
     int na[BUILD_TAB]; // members in plane 0
-    int ncell, total, fits, NX;
+    int mp[2 * BUILD_MAX_NX + 1]; // member prefix: own-row cells' plane-0 members, then plane-1
+    int ncell, total, fits, NX, own0, nown;
 };
 
 // Candidate e of a staged cell: plane-0 member e, else plane-1 member e - na
@@ -640,20 +641,17 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
         const RepDev rp = a.rep[s];
         const int nd = rp.nd, planes = rp.planes, nc = nd * nd * nd;
         const int *cs = a.cs_new + rp.coff;
-        // members: the segment's slots of plane 0 ([sm0, sm0 + ms0)), then
-        // those of plane 1; this item builds member indices [m0, m1)
-        int m0, m1, sm0, ms0, sm1, NX = 1;
+        int NX = 1, part = 0;
         bool full = true;
         if (nd == 1) {
-            sm0 = rp.off; ms0 = rp.n; sm1 = rp.off + rp.n; // the planes are adjacent slots
-            m0 = item * a.single_members;
-            m1 = min(m0 + a.single_members, rp.n);
             if (t == 0) {
                 const int na = cs[1] - cs[0];
                 T.pk[0] = make_int4(0, rp.n, cs[0], planes > 1 ? cs[1] : cs[0] + na);
                 T.na[0] = na;
                 T.ncell = 1;
                 T.NX = 1;
+                T.own0 = 0;
+                T.nown = 1;
                 T.total = rp.n;
                 T.fits = rp.n <= a.lds_cap;
                 if (item == 0 && a.from_scratch)
@@ -663,23 +661,19 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             const int W = a.width;
             full = nd <= W + 2;
             const int nseg = full ? 1 : (nd + W - 1) / W;
-            const int part = item % rp.bparts, segitem = item / rp.bparts;
+            part = item % rp.bparts;
+            const int segitem = item / rp.bparts;
             const int seg = segitem % nseg, row = segitem / nseg;
             const int cy = row % nd, cz = row / nd;
             const int x0 = full ? 0 : (seg * nd) / nseg; // balanced segments
             const int x1 = full ? nd : ((seg + 1) * nd) / nseg;
             NX = full ? nd : x1 - x0 + 2;
             const int rowbase = nd * (cy + nd * cz);
-            sm0 = cs[rowbase + x0];
-            ms0 = cs[rowbase + x1] - sm0;
-            sm1 = planes > 1 ? cs[nc + rowbase + x0] : 0;
-            const int ms = ms0 + (planes > 1 ? cs[nc + rowbase + x1] - sm1 : 0);
-            // this item's share of the segment's members
-            m0 = (int)(((long long)part * ms) / rp.bparts);
-            m1 = (int)(((long long)(part + 1) * ms) / rp.bparts);
             if (a.from_scratch && part == 0) { // retire the old cell starts of this segment
-                for (int pl = 0; pl < planes; ++pl)
-                    for (int k = x0 + t; k < x1; k += B) a.cs[rp.coff + pl * nc + rowbase + k] = cs[pl * nc + rowbase + k];
+                for (int k = x0 + t; k < x1; k += B) {
+                    const int rk = cell_rank(rowbase + k, rp, a.corder);
+                    for (int pl = 0; pl < planes; ++pl) a.cs[rp.coff + pl * nc + rk] = cs[pl * nc + rk];
+                }
                 if (t == 0 && rowbase + x1 == nc) a.cs[rp.coff + planes * nc] = cs[planes * nc];
             }
             const int gs = full ? 0 : (x0 - 1 + nd) % nd; // first staged x
@@ -691,14 +685,19 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
                 int gy = cy + dy, gz = cz + dz;
                 gy += gy < 0 ? nd : 0; gy -= gy >= nd ? nd : 0;
                 gz += gz < 0 ? nd : 0; gz -= gz >= nd ? nd : 0;
-                const int cc = gx + nd * (gy + nd * gz);
-                const int ga = cs[cc], na = cs[cc + 1] - ga;
-                const int gb = planes > 1 ? cs[nc + cc] : ga + na;
-                const int nb = planes > 1 ? cs[nc + cc + 1] - gb : 0;
+                const int rk = cell_rank(gx + nd * (gy + nd * gz), rp, a.corder);
+                const int ga = cs[rk], na = cs[rk + 1] - ga;
+                const int gb = planes > 1 ? cs[nc + rk] : ga + na;
+                const int nb = planes > 1 ? cs[nc + rk + 1] - gb : 0;
                 T.pk[k] = make_int4(0, na + nb, ga, gb);
                 T.na[k] = na;
             }
-            if (t == 0) { T.NX = NX; T.ncell = 9 * NX; }
+            if (t == 0) {
+                T.NX = NX;
+                T.ncell = 9 * NX;
+                T.own0 = 4 * NX + (full ? 0 : 1); // own row (dz = dy = 0), segment cells
+                T.nown = full ? NX : NX - 2;
+            }
             __syncthreads();
             if (t < 64) { // exclusive scan of the staged cell sizes (one wave)
                 const int ncells = 9 * NX;
@@ -719,6 +718,13 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             }
         }
         __syncthreads();
+        if (t == 0) { // member prefix over the segment's cells: plane 0 members, then plane 1
+            const int o = T.own0, no = T.nown;
+            int acc = 0;
+            T.mp[0] = 0;
+            for (int j = 0; j < no; ++j) { acc += T.na[o + j]; T.mp[j + 1] = acc; }
+            for (int j = 0; j < no; ++j) { acc += T.pk[o + j].y - T.na[o + j]; T.mp[no + j + 1] = acc; }
+        }
         const bool fits = T.fits != 0;
         if (fits) { // stage: element e belongs to the last cell whose LDS start is <= e
             const int tot = T.total, ncl = T.ncell;
@@ -737,16 +743,27 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             }
         }
         __syncthreads();
-        // member index -> slot, and the member's own-row staged cell (the
-        // last one whose start in the member's plane is <= i)
-        auto slot_of = [&](int k) { return k < ms0 ? sm0 + k : sm1 + (k - ms0); };
-        auto member_cell = [&](int i, int k) {
-            if (nd == 1) return 0;
-            const bool b = k >= ms0;
-            int lx = full ? 0 : 1;
-            const int le = full ? NX - 1 : NX - 2;
-            while (lx < le && (b ? T.pk[4 * NX + lx + 1].w : T.pk[4 * NX + lx + 1].z) <= i) ++lx;
-            return lx;
+        // this item's share of the segment's members
+        const int no = T.nown, ms = T.mp[2 * no];
+        int m0, m1;
+        if (nd == 1) {
+            m0 = item * a.single_members;
+            m1 = min(m0 + a.single_members, rp.n);
+        } else {
+            m0 = (int)(((long long)part * ms) / rp.bparts);
+            m1 = (int)(((long long)(part + 1) * ms) / rp.bparts);
+        }
+        // member index k -> slot i and the member's own-row staged cell lx
+        auto member = [&](int k, int &i, int &lx) {
+            int lo = 0, hi = 2 * no; // last j with mp[j] <= k
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (T.mp[mid] <= k) lo = mid; else hi = mid;
+            }
+            const int jj = lo < no ? lo : lo - no;
+            const int4 c = T.pk[T.own0 + jj];
+            i = (lo < no ? c.z : c.w) + (k - T.mp[lo]);
+            lx = nd == 1 ? 0 : T.own0 + jj - 4 * NX;
         };
         // lanes per member: the replica's (fixed by the launch, or one lane
         // for large replicas), else the largest power of two that still
@@ -758,7 +775,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
         }
         if (G == 1) {
             for (int k = m0 + t; k < m1; k += B) {
-                const int i = slot_of(k), lx_m = member_cell(i, k);
+                int i, lx_m;
+                member(k, i, lx_m);
                 if (fits) build_member<P, true>(a, rp, i, lx_m, T, full, cand, s, nd);
                 else build_member<P, false>(a, rp, i, lx_m, T, full, cand, s, nd);
                 copy_back<P>(a, i);
@@ -769,7 +787,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
                 G == 64 ? ~0ull : ((1ull << G) - 1ull) << (lane & ~(G - 1));
             const unsigned long long below = (1ull << lane) - 1ull;
             for (int k = m0 + t / G; k < m1; k += B / G) {
-                const int i = slot_of(k), lx_m = member_cell(i, k);
+                int i, lx_m;
+                member(k, i, lx_m);
                 if (fits) build_member_grp<P, true>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
                 else build_member_grp<P, false>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
                 if (gl == 0) copy_back<P>(a, i);

@@ -399,6 +399,19 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
 
     State<P> st;
     st.load(A, i);
+    // With a curve cell order, read the rank of the particle's current cell
+    // now, off the critical path: a particle usually stays in its cell, and
+    // the table is read again at the end only when the cell changed.
+    int cell0 = -1, rank0 = 0;
+    if (!OBS && rp.curve) {
+        if constexpr (P == PREC_FP64) {
+            double x0, y0, z0, w0;
+            u4_to_dbl2(s0, x0, y0);
+            u4_to_dbl2(s1, z0, w0);
+            cell0 = dbl_cell(x0, y0, z0, rp.L, rp.invL, rp.nd);
+        } else cell0 = fixed_cell(s0.x, s0.y, s0.z, rp.nd);
+        rank0 = a.corder[rp.coff + cell0];
+    }
 
     if constexpr (P == PREC_FP64) {
         double xi, yi, zi, wi;
@@ -498,7 +511,8 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         else bad = !isfinite(st.x + st.y + st.z);
         cell = rp.nd == 1 ? 0 : fixed_cell(X.x, X.y, X.z, rp.nd);
     }
-    atomicAdd(a.count_cur + rp.coff + sort_key(cell, meta, rp.planes, rp.nd), 1);
+    const int rank = cell == cell0 ? rank0 : cell_rank(cell, rp, a.corder);
+    atomicAdd(a.count_cur + rp.coff + sort_key(rank, meta, rp.planes, rp.nd), 1);
     if (far && atomicOr(a.need_cur + r, 1) == 0) { // first to flag: enlist the slot
         const int k = atomicAdd(a.rlist_cur, 1);
         a.rlist_cur[1 + k] = r;

@@ -34,8 +34,10 @@ EXPORTS = [
     "md_save", "md_restore", "md_debug_neighbours", "md_get_launch",
     "md_set_launch", "md_ds_eval", "md_strerror", "md_last_error",
     "md_abi_version", "md_tcf_workspace_bytes", "md_tcf_create", "md_tcf_sample",
-    "md_tcf_read", "md_tcf_destroy", "md_thermostat",
+    "md_tcf_read", "md_tcf_destroy", "md_thermostat", "md_cell_order",
 ]
+
+CELL_ORDERS = {"row": 0, "morton": 1, "hilbert": 2}
 
 
 class MdConfig(ctypes.Structure):
@@ -46,7 +48,7 @@ class MdConfig(ctypes.Structure):
                 ("nbr_capacity", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("max_particles", ctypes.c_int64), ("max_cells", ctypes.c_int64),
                 ("max_density", ctypes.c_double), ("lanes_per_particle", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("smooth", ctypes.c_double)]
+                ("cell_order", ctypes.c_int32), ("smooth", ctypes.c_double)]
 
 
 class MdReplica(ctypes.Structure):
@@ -134,6 +136,7 @@ def load():
         "md_strerror": (ctypes.c_char_p, [i32]),
         "md_last_error": (ctypes.c_char_p, [vp]),
         "md_abi_version": (i32, []),
+        "md_cell_order": (i32, [i32, i32, ip]),
         "md_tcf_workspace_bytes": (i64, [i32, i32, i32]),
         "md_tcf_create": (i32, [vp, i32, i32, i32, ctypes.c_double, vp, i64, ctypes.POINTER(vp)]),
         "md_tcf_sample": (i32, [vp]),
@@ -160,7 +163,7 @@ def _ip(a: np.ndarray):
 def make_config(table, precision, dt: float, skin: float, max_slots: int,
                 max_particles: int, mass: float = 1.0, nbr_capacity: int = 0,
                 max_cells: int = 0, max_density: float = 0.0,
-                lanes_per_particle: int = 0) -> MdConfig:
+                lanes_per_particle: int = 0, cell_order="row") -> MdConfig:
     """md_config from a pair table (md_inputs.PairTable, including its
     smoothing width) and run parameters."""
     if isinstance(precision, str):
@@ -181,7 +184,19 @@ def make_config(table, precision, dt: float, skin: float, max_slots: int,
     c.max_density = float(max_density)
     c.lanes_per_particle = int(lanes_per_particle)
     c.smooth = float(getattr(table, "smooth", 0.0))
+    c.cell_order = CELL_ORDERS[cell_order] if isinstance(cell_order, str) else int(cell_order)
     return c
+
+
+def cell_order_ranks(nd: int, order) -> np.ndarray:
+    """md_cell_order: rank of every cell c = x + nd (y + nd z) of an nd^3
+    grid in the given cell order (host only)."""
+    o = CELL_ORDERS[order] if isinstance(order, str) else int(order)
+    out = np.zeros(nd ** 3, dtype=np.int32)
+    st = int(load().md_cell_order(int(nd), o, _ip(out)))
+    if st != 0:
+        raise MdError(st, f"md_cell_order(nd={nd}, order={order})")
+    return out
 
 
 def md_workspace_bytes(cfg: MdConfig) -> int:

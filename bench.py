@@ -137,6 +137,7 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=20240101)
+    ap.add_argument("--skin", type=float, default=None, help="Verlet skin (default: the workload's)")
     ap.add_argument("--cell-order", default="row", choices=["row", "morton", "hilbert"],
                     help="order of the cells in the particle sort")
     ap.add_argument("--calib-copy", action="store_true",
@@ -152,12 +153,14 @@ def main():
     from paper_0912_3824_amd import mdx
 
     desc, default_prec = WORKLOADS[args.workload]
+    if args.skin is not None:
+        desc = desc.replace("skin=0.3", f"skin={args.skin:g}")
     prec = args.precision or default_prec
     systems = build_systems(args.workload, args.seed)
     n_total = sum(s.n for s in systems)
     log(f"workload {args.workload}: {len(systems)} replica(s), {n_total} particles, precision {prec}")
 
-    pool = mdx.md_init(systems, prec, cell_order=args.cell_order)
+    pool = mdx.md_init(systems, prec, skin=args.skin, cell_order=args.cell_order)
     from paper_0912_3824_amd import tune
     tuned = tune.apply_cached(pool)  # launch shapes from the autotuner, if tuned
     pool.set_launch(graph_steps=args.graph_steps)
@@ -245,7 +248,8 @@ def main():
                   "mixed64": "f32 pair term, f64 sum and integration", "fp64": "f64"}[prec],
         "data": "synthetic (seeded fcc-subset start, Maxwell-Boltzmann velocities, rescaled equilibration)",
         "config": {"workload": args.workload, "description": desc, "particles": n_total,
-                   "replicas": len(systems), "precision": prec, "skin": systems[0].skin,
+                   "replicas": len(systems), "precision": prec,
+                   "skin": args.skin if args.skin is not None else systems[0].skin,
                    "cell_order": args.cell_order,
                    "graph_steps": args.graph_steps, "equil_steps": args.equil,
                    "launch": pool.get_launch(),

@@ -113,7 +113,8 @@ typedef struct {
     double skin;           /* Verlet skin; > 0 */
     int32_t nbr_capacity;  /* list entries per particle; 0 = derive from max_density */
     int32_t max_slots;     /* replicas attachable at once; >= 1 */
-    int64_t max_particles; /* particle arena capacity; >= 1 */
+    int64_t max_particles; /* particle arena capacity: 1 .. 2^28 - 256 (Verlet-list
+                              entries are 32-bit byte offsets of 16-byte records) */
     int64_t max_cells;     /* cell arena capacity; 0 = derive from max_particles */
     double max_density;    /* density used to derive capacities; 0 = 1.2 */
     int32_t lanes_per_particle; /* lanes summing one particle's list: 1, 2 or 4

@@ -174,7 +174,7 @@ static md_status validate_cfg(const md_config *c, std::string *why)
     if (!(c->mass > 0) || !(c->dt > 0) || !(c->skin > 0) || !std::isfinite(c->dt) || !std::isfinite(c->skin))
         return bad("mass, dt and skin must be positive");
     if (c->max_slots < 1 || c->max_slots > 65536) return bad("max_slots must be in [1, 65536]");
-    if (c->max_particles < 1 || c->max_particles > (int64_t)1 << 30) return bad("max_particles must be in [1, 2^30]");
+    if (c->max_particles < 1 || c->max_particles > MAX_ARENA_SLOTS - 256) return bad("max_particles must be in [1, 2^28 - 256]");
     if (c->nbr_capacity < 0 || c->nbr_capacity > 4096) return bad("nbr_capacity must be in [0, 4096]");
     if (c->max_cells < 0) return bad("max_cells must be >= 0");
     if (c->max_density < 0) return bad("max_density must be >= 0");
@@ -782,7 +782,7 @@ static int cell_of_snap(const md_system *s, const RepDev &r, const uint4 *sn)
     return fixed_cell(sn[0].x, sn[0].y, sn[0].z, r.nd);
 }
 
-static uint32_t meta_word(int slot, int species) { return ((uint32_t)slot << SLOT_SHIFT) | (uint32_t)(species & 1); }
+static uint32_t meta_word(int slot, int species) { return ((uint32_t)(species & 1) << 31) | ((uint32_t)slot << SLOT_SHIFT); }
 
 static md_status validate_rep(md_system *s, const md_replica *rep)
 {
@@ -1548,9 +1548,9 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
             if (H.NS == 2) {
                 double z, w;
                 get_dbl2((*v)[n + k], z, w);
-                put_dbl2((*v)[n + k], z, bits_of_meta(meta_word(slot, meta_of_bits(w) & 1)));
+                put_dbl2((*v)[n + k], z, bits_of_meta(meta_word(slot, species_of(meta_of_bits(w)))));
             } else {
-                (*v)[k].w = meta_word(slot, (*v)[k].w & 1);
+                (*v)[k].w = meta_word(slot, species_of((*v)[k].w));
             }
         }
         uint4 sn[2] = {xr[k], H.NS == 2 ? xr[n + k] : make_uint4(0, 0, 0, 0)};
@@ -1599,7 +1599,7 @@ md_status md_debug_neighbours(md_system *s, int32_t slot, int32_t *counts, int32
         for (int q = 0; q < cap; ++q) {
             int v = -1;
             if (q < cnt[k] && q < lc) {
-                int j = lst[(size_t)(q >> 2) * 4 * n + 4 * k + (q & 3)] - (int)h.off;
+                int j = list_slot(lst[(size_t)(q >> 2) * 4 * n + 4 * k + (q & 3)]) - (int)h.off;
                 v = (j >= 0 && j < n) ? mt[j].w : -2;
             }
             ids[(size_t)id * cap + q] = v;

@@ -52,7 +52,7 @@ __device__ __forceinline__ int remap_block(int b, int nblk, int on)
     return b;
 }
 
-__device__ __forceinline__ int slot_of_meta(uint32_t w) { return (int)(w >> SLOT_SHIFT); }
+__device__ __forceinline__ int slot_of_meta(uint32_t w) { return (int)((w & 0x7FFFFFFFu) >> SLOT_SHIFT); }
 
 // Rank of cell c (= x + nd (y + nd z)) in the replica's cell order: itself
 // in row-major order, else from the replica's rank table (a space-filling

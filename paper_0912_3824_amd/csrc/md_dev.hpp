@@ -7,7 +7,9 @@
 //   snapshot      : uint4 snap[2][NS][P]  ping-pong, read by neighbours
 //   reference pos : uint4 xref[NS][P]     positions at the last list build
 //   meta          : int4 meta[P]          (image x, image y, image z, id)
-//   list count    : int nbr_cnt[P];  list: int nbr[cap][P] (column-major)
+//   list count    : int nbr_cnt[P];  list: int nbr[cap][P] (column-major;
+//                   an entry is the neighbour's slot times 16, the byte
+//                   offset of its 16-byte snapshot record)
 //   observation   : double obs[P][8]      (fx, fy, fz, e_i, w_i, vx, vy, vz)
 // plus a scratch copy of st/snap/meta used by the cell sort.
 //
@@ -15,7 +17,8 @@
 // MIXED64 paths it is a 32-bit fixed-point copy of the position,
 // X = round(x * 2^32 / L) mod 2^32, so that the minimum image is the int32
 // wrap-around of X_i - X_j and a pair separation is exact before it is
-// converted to float.  Its w word holds (slot << 4) | species.  The FP64
+// converted to float.  Its w word holds species << 31 | slot << 4 (the
+// species in the sign bit, so one compare tests it).  The FP64
 // path keeps double positions (two words: x,y | z,w) and the textbook
 // minimum image.
 #pragma once
@@ -105,8 +108,15 @@ __host__ __device__ __forceinline__ double bits_of_meta(uint32_t m)
 }
 
 #define SLOT_SHIFT 4
-#define SPECIES_MASK 1u
+#define MAX_ARENA_SLOTS (1 << 28) // list entries are 32-bit byte offsets (slot x 16)
+
+// List entry of slot j: the byte offset of its snapshot record.
+__host__ __device__ __forceinline__ int list_entry(int j) { return (int)((uint32_t)j << 4); }
+__host__ __device__ __forceinline__ int list_slot(int e) { return (int)((uint32_t)e >> 4); }
 #define NO_SLOT 0xFFFFFFFFu
+
+// Species (0 = A, 1 = B) of a meta word.
+__host__ __device__ __forceinline__ int species_of(uint32_t w) { return (int)(w >> 31); }
 
 // ---------------------------------------------------------------- fixed point
 __host__ __device__ __forceinline__ uint32_t to_fixed(double x, double fxs)
@@ -147,7 +157,7 @@ __host__ __device__ __forceinline__ int dbl_cell1(double x, double L, double inv
 // whose lists are of similar length.
 __host__ __device__ __forceinline__ int sort_key(int rank, uint32_t meta, int planes, int nd)
 {
-    return planes > 1 ? (int)(meta & SPECIES_MASK) * nd * nd * nd + rank : rank;
+    return planes > 1 ? species_of(meta) * nd * nd * nd + rank : rank;
 }
 
 __host__ __device__ __forceinline__ int dbl_cell(double x, double y, double z, double L, double invL, int nd)

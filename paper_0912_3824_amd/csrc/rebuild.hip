@@ -346,7 +346,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         u4_to_dbl2(a.src_x[P_ + i], zd, wd);
         meta = meta_of_bits(wd);
     } else meta = xi.w;
-    const int si = (int)(meta & SPECIES_MASK);
+    const int si = species_of(meta);
     float rl2s0, rl2s1;
     double rl2d0 = a.pp.rl2d[si * 2], rl2d1 = a.pp.rl2d[si * 2 + 1];
     {
@@ -383,13 +383,13 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             dy -= rp.L * rint(dy * rp.invL);
             dz -= rp.L * rint(dz * rp.invL);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
+            return r2 < (species_of(meta_of_bits(wj)) ? rl2d1 : rl2d0);
         }
         const uint4 xj = q.a;
         const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
                     dz = (float)(int)(xi.z - xj.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
+        return r2 < (((int)xj.w < 0) ? rl2s1 : rl2s0);
     };
     // The candidates of staged cell k in order (i itself is skipped).  Each
     // chunk of up to 64 candidates is tested four at a time (independent
@@ -420,7 +420,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             while (mask) {
                 const int b = __ffsll((long long)mask) - 1;
                 mask &= mask - 1;
-                if (cnt < cap) col[4 * ((unsigned long long)(unsigned)(cnt >> 2) * (unsigned)P_) + (cnt & 3)] = cand_glob(c, na, base + b);
+                if (cnt < cap) col[4 * ((unsigned long long)(unsigned)(cnt >> 2) * (unsigned)P_) + (cnt & 3)] = list_entry(cand_glob(c, na, base + b));
                 ++cnt;
             }
         }
@@ -463,7 +463,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         }
         if (pad < 0) atomicOr(a.status + s, 8);
         for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
-            col[(size_t)(k >> 2) * row_stride + (k & 3)] = pad < 0 ? i : pad;
+            col[(size_t)(k >> 2) * row_stride + (k & 3)] = list_entry(pad < 0 ? i : pad);
     }
     A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
     if (cnt > A.cap) atomicOr(a.status + s, 1);
@@ -494,7 +494,7 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
         u4_to_dbl2(a.src_x[P_ + i], zd, wd);
         meta = meta_of_bits(wd);
     } else meta = xi.w;
-    const int si = (int)(meta & SPECIES_MASK);
+    const int si = species_of(meta);
     float rl2s0, rl2s1;
     double rl2d0 = a.pp.rl2d[si * 2], rl2d1 = a.pp.rl2d[si * 2 + 1];
     {
@@ -521,13 +521,13 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
             dy -= rp.L * rint(dy * rp.invL);
             dz -= rp.L * rint(dz * rp.invL);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            return r2 < ((meta_of_bits(wj) & 1) ? rl2d1 : rl2d0);
+            return r2 < (species_of(meta_of_bits(wj)) ? rl2d1 : rl2d0);
         }
         const uint4 xj = FROM_LDS ? cand[x] : a.src_x[x];
         const float dx = (float)(int)(xi.x - xj.x), dy = (float)(int)(xi.y - xj.y),
                     dz = (float)(int)(xi.z - xj.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        return r2 < ((xj.w & SPECIES_MASK) ? rl2s1 : rl2s0);
+        return r2 < (((int)xj.w < 0) ? rl2s1 : rl2s0);
     };
     // one cell's candidates (in the one-lane build's order), 4G at a time:
     // lane gl tests e = b + u G + gl (u = 0..3, independent loads in
@@ -550,7 +550,7 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
                 const unsigned long long m = __ballot(acc[u]) & gmask;
                 if (acc[u]) {
                     const int k2 = cnt + __popcll(m & below);
-                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = g[u];
+                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = list_entry(g[u]);
                 }
                 cnt += __popcll(m);
             }
@@ -601,7 +601,7 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
             }
             if (pad < 0) atomicOr(a.status + s, 8);
             for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
-                col[(size_t)(k >> 2) * row_stride + (k & 3)] = pad < 0 ? i : pad;
+                col[(size_t)(k >> 2) * row_stride + (k & 3)] = list_entry(pad < 0 ? i : pad);
         }
     }
     if (gl == 0) {

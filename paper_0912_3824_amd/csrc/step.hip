@@ -174,7 +174,7 @@ __device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts
     const int ix = (int)(xi.x - xj.x), iy = (int)(xi.y - xj.y), iz = (int)(xi.z - xj.z);
     const float dx = (float)ix, dy = (float)iy, dz = (float)iz;
     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-    const bool b = (xj.w & SPECIES_MASK) != 0;
+    const bool b = (int)xj.w < 0; // species B (sign bit of the meta word)
     const float sig2 = b ? c.sig2s[1] : c.sig2s[0];
     const float e24 = b ? c.e24s[1] : c.e24s[0];
     const float ir2 = __builtin_amdgcn_rcpf(r2);
@@ -215,9 +215,10 @@ __device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts
 }
 
 // Snapshot gather with a 32-bit byte offset from a uniform base.
-__device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int j)
+// snapshot record at list entry e (a byte offset, see list_entry)
+__device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int e)
 {
-    return *(const uint4 *)((const char *)snap + (uint32_t)j * 16u);
+    return *(const uint4 *)((const char *)snap + (uint32_t)e);
 }
 
 // Force (and optionally energy/virial) on particle i from its list.  The
@@ -292,7 +293,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
         const int js[4] = {jj.x, jj.y, jj.z, jj.w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int j = js[u]; // padding entries lie beyond the cutoff
+            const int j = list_slot(js[u]); // padding entries lie beyond the cutoff
             double xj, yj, zj, wj;
             u4_to_dbl2(snap[j], xj, yj);
             u4_to_dbl2(snap1[j], zj, wj);
@@ -301,7 +302,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
             dy -= r.L * rint(dy * r.invL);
             dz -= r.L * rint(dz * r.invL);
             double r2 = dx * dx + dy * dy + dz * dz;
-            int b = meta_of_bits(wj) & 1;
+            int b = species_of(meta_of_bits(wj));
             double ir2 = 1.0 / r2;
             double s2 = sig2[b] * ir2;
             double s6 = s2 * s2 * s2;
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
             return;
         }
     }
-    const int si = (int)(meta & SPECIES_MASK);
+    const int si = species_of(meta);
     double e_sum = 0.0, w_sum = 0.0;
     double fxd, fyd, fzd;
 
@@ -512,7 +513,18 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         cell = rp.nd == 1 ? 0 : fixed_cell(X.x, X.y, X.z, rp.nd);
     }
     const int rank = cell == cell0 ? rank0 : cell_rank(cell, rp, a.corder);
-    atomicAdd(a.count_cur + rp.coff + sort_key(rank, meta, rp.planes, rp.nd), 1);
+    // Count the particle in its new cell.  The wave's particles are sorted by
+    // cell, so most of its lanes count into one or two cells: one lane per
+    // distinct cell adds the number of lanes with that cell, instead of
+    // every lane contending for the same counter.
+    int *ctr = a.count_cur + rp.coff + sort_key(rank, meta, rp.planes, rp.nd);
+    for (unsigned long long todo = __ballot(1); todo;) {
+        const int leader = __ffsll((long long)todo) - 1;
+        int *lc = (int *)__shfl((long long)ctr, leader, 64);
+        const unsigned long long same = __ballot(lc == ctr);
+        if (__lane_id() == leader) atomicAdd(lc, __popcll(same));
+        todo &= ~same;
+    }
     if (far && atomicOr(a.need_cur + r, 1) == 0) { // first to flag: enlist the slot
         const int k = atomicAdd(a.rlist_cur, 1);
         a.rlist_cur[1 + k] = r;

@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(TCF_BLOCK) k_tcf_store(const TcfArgs a, int en
     const size_t e = (size_t)entry * a.n + id;
     a.pos[e] = make_double4(r[0], r[1], r[2], 0.0);
     a.vel[e] = make_double4(v[0], v[1], v[2], 0.0);
-    a.species[id] = (int)(meta & SPECIES_MASK);
+    a.species[id] = species_of(meta);
 }
 
 __device__ __forceinline__ double tcf_wave_sum(double x)

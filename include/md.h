@@ -167,7 +167,11 @@ typedef struct {
                             * smaller replicas split each segment's members over several
                             * work items, each using the most lanes that keep one group per
                             * member (16 for single-cell replicas) */
-    int32_t reserved[2];
+    int32_t build_split;   /* most list-build work items one row segment is split into (the
+                            * members of a small replica's segments are shared out): 0 =
+                            * automatic (up to 256 / segments per replica), 1 = no split,
+                            * up to 256 */
+    int32_t reserved;
 } md_launch;
 
 /* ---- sizing and lifetime ------------------------------------------------ */

@@ -362,6 +362,7 @@ static void build_shape(const md_system *s, int n, int nd, int &parts, int &lane
         return;
     }
     parts = std::max(1, std::min((256 + base - 1) / base, n / base / 16));
+    if (s->launch.build_split > 0) parts = std::min(parts, s->launch.build_split);
 }
 
 static int items4_of(const md_system *s, int n, int nd)
@@ -948,6 +949,8 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     s->launch.graph_steps = 32;
     s->launch.xcd_remap = 0;
     s->launch.build_lanes = 0;
+    s->launch.build_split = 0;
+    s->launch.reserved = 0;
     make_tables(s);
     {
         int dev = 0;
@@ -1626,6 +1629,7 @@ md_status md_set_launch(md_system *s, const md_launch *in)
         return fail(s, MD_E_ARG, "bad build_lanes");
     if (l.graph_steps != 0 && (l.graph_steps < 2 || l.graph_steps > 256 || l.graph_steps % 2))
         return fail(s, MD_E_ARG, "bad graph_steps");
+    if (l.build_split < 0 || l.build_split > 256) return fail(s, MD_E_ARG, "bad build_split");
     drop_graphs(s);
     const md_launch prev = s->launch;
     s->launch = l;

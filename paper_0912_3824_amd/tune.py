@@ -1,8 +1,8 @@
 """Autotuner of libmdx launch shapes.
 
 The knobs (md_launch: block size of the fused step kernel, cells per LDS row
-segment, block size and lanes per member of the list build, steps per
-captured hipGraph, XCD-aware tile mapping) change no result bit: lists are in a canonical order and
+segment, block size, lanes per member and segment split of the list build,
+steps per captured hipGraph, XCD-aware tile mapping) change no result bit: lists are in a canonical order and
 every particle sums its own list sequentially.  The tuner therefore times
 candidate shapes on the live pool, from a saved checkpoint so that every
 candidate advances the same trajectory, and keeps the fastest.  Results are
@@ -26,6 +26,7 @@ SPACE = {
     "build_lanes": [0, 16],
     "graph_steps": [32],
     "xcd_remap": [0, 1],
+    "build_split": [0, 4],
 }
 
 

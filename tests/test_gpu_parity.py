@@ -83,15 +83,16 @@ def test_list_build_lanes_give_identical_lists(prec, n):
     s = _ka(n)
     pool = pool_for([s], prec)
     ref = None
-    for lanes, block, width in [(1, 256, 4), (2, 256, 4), (4, 512, 1), (8, 1024, 2), (16, 256, 8),
-                                (32, 64, 4), (64, 1024, 4), (0, 512, 8), (0, 64, 1)]:
-        pool.set_launch(build_lanes=lanes, build_block=block, build_width=width)
+    for lanes, block, width, split in [(1, 256, 4, 0), (2, 256, 4, 0), (4, 512, 1, 0), (8, 1024, 2, 0),
+                                       (16, 256, 8, 0), (32, 64, 4, 0), (64, 1024, 4, 0), (0, 512, 8, 0),
+                                       (0, 64, 1, 0), (0, 512, 8, 1), (16, 512, 4, 3), (0, 256, 2, 256)]:
+        pool.set_launch(build_lanes=lanes, build_block=block, build_width=width, build_split=split)
         pool.rebuild_neighbours()
         cnt, ids = pool.neighbours(0, cap=256)
-        say("lanes", prec, n, lanes, block, width, "entries", int(cnt.sum()))
+        say("lanes", prec, n, lanes, block, width, split, "entries", int(cnt.sum()))
         if ref is None:
             ref = (cnt, ids)
-        assert np.array_equal(cnt, ref[0]) and np.array_equal(ids, ref[1]), (lanes, block, width)
+        assert np.array_equal(cnt, ref[0]) and np.array_equal(ids, ref[1]), (lanes, block, width, split)
     pool.close()
 
 

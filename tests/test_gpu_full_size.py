@@ -1,0 +1,148 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (the autotuner's cached shapes): the N = 1M and N = 64k Kob-Andersen
+systems and the 256-replica ensemble.  The oracle computes forces, energies
+and list membership for a random sample of particles one by one against all
+N (brute force); whole-system dynamics are checked through properties that
+hold at any size (momentum and energy conservation, time reversibility).
+The oracle always receives the state the device holds (md_get_state)."""
+import math
+
+import numpy as np
+import pytest
+
+import md_inputs as I
+from oracle import oracle as O
+from gpu_helpers import TOL_F, pool_for, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _tuned_pool(systems, prec):
+    from paper_0912_3824_amd import tune
+    pool = pool_for(systems, prec)
+    shape = tune.apply_cached(pool)
+    say("launch", pool.get_launch(), "(cached)" if shape else "(defaults)")
+    return pool
+
+
+def _band_mask(pos, box, species, table, sel, radius_of, band):
+    """Sampled particles with a pair within a relative `band` of radius_of."""
+    from scipy.spatial import cKDTree
+    p = np.mod(pos, box)
+    p[p >= box] = 0.0
+    tree = cKDTree(p, boxsize=box)
+    rm = max(radius_of(a, b) for a in range(2) for b in range(2)) * (1 + 2 * band)
+    out = np.zeros(len(sel), dtype=bool)
+    sp = species if table.n_species > 1 else np.zeros(len(pos), dtype=int)
+    for k, i in enumerate(sel):
+        js = np.array([j for j in tree.query_ball_point(p[i], rm) if j != i], dtype=np.int64)
+        if len(js) == 0:
+            continue
+        d = p[js] - p[i]
+        d -= box * np.rint(d / box)
+        r = np.sqrt((d * d).sum(axis=1))
+        rad = np.array([radius_of(sp[i], sp[j]) for j in js])
+        out[k] = bool(np.any(np.abs(r - rad) < band * rad))
+    return out
+
+
+def _sampled_parity(pool, slot, s, prec, m, seed, check_lists=True):
+    pos, vel, img = pool.get_state(slot)
+    f, e = pool.forces(slot)
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(s.n, size=min(m, s.n), replace=False)).astype(np.int32)
+    fr, er, _ = O.forces(pos, s.box, s.species, s.table, sel)
+    frms = math.sqrt(float(np.mean(f * f)))  # over the whole system
+    excl = np.zeros(len(sel), dtype=bool)
+    if prec != "fp64":
+        excl = _band_mask(pos, s.box, s.species, s.table, sel, lambda a, b: s.table.rcut[a, b], 2e-6)
+    d = np.abs(f[sel] - fr)
+    # relative error of each sampled particle's force, against its own
+    # magnitude with F_rms as the floor (a near-zero force has no useful
+    # relative error); the F_rms-normalised component maximum is reported too
+    rel = np.linalg.norm(f[sel] - fr, axis=1) / np.maximum(np.linalg.norm(fr, axis=1), frms)
+    err = float(rel[~excl].max())
+    say("  sampled", len(sel), "of", s.n, "relative error", err, "max component error / F_rms",
+        float(d[~excl].max()) / frms, "F_rms", frms, "excluded", int(excl.sum()))
+    assert err < TOL_F[prec]
+    if excl.any():  # one cutoff jump at most
+        jump = abs(O.pair(s.table.rcut[0, 0] * (1 - 1e-12), 1.5, 0.8, 2.0)[1])
+        assert d[excl].max() < 2 * jump + TOL_F[prec] * frms
+    scale = max(1.0, float(np.abs(er).max()))
+    assert float(np.abs(e[sel] - er)[~excl].max()) < (1e-10 if prec == "fp64" else 1e-5) * scale
+    if check_lists:
+        # Verlet-list validity at the current positions (the lists were built
+        # up to skin/2 of motion ago): every pair inside its cutoff is listed
+        cnt, ids = pool.neighbours(slot, cap=160)
+        inside = O.neighbours(pos, s.box, s.species, s.table, 0.0, sel)
+        for k, i in enumerate(sel):
+            got = set(ids[i, :cnt[i]].tolist())
+            assert len(got) == cnt[i]  # no duplicates
+            missing = set(inside[k].tolist()) - got
+            assert not missing or excl[k], (int(i), sorted(missing))
+        # exact membership right after a build
+        pool.rebuild_neighbours()
+        pos, vel, img = pool.get_state(slot)
+        cnt, ids = pool.neighbours(slot, cap=160)
+        ref = O.neighbours(pos, s.box, s.species, s.table, s.skin, sel)
+        amb = _band_mask(pos, s.box, s.species, s.table, sel, lambda a, b: s.table.rcut[a, b] + s.skin, 1e-6)
+        bad = 0
+        for k, i in enumerate(sel):
+            got = ids[i, :cnt[i]]
+            assert len(set(got.tolist())) == cnt[i]
+            if set(got.tolist()) != set(ref[k].tolist()):
+                assert amb[k], (int(i), sorted(set(got.tolist()) ^ set(ref[k].tolist())))
+                bad += 1
+        say("  lists: cutoff pairs all listed; after a build the sample equals the oracle; band cases", bad)
+
+
+def test_ka1m_sampled_forces_lists_and_dynamics():
+    """N = 1,000,000 KA at T = 0.5 in double-single (the benchmark system)."""
+    s = I.make_ka(1_000_000, 0.5, seed=20240101)
+    pool = _tuned_pool([s], "ds")
+    pool.step(200)
+    _sampled_parity(pool, 0, s, "ds", 256, seed=5)
+    # dynamics at full size: momentum stays zero, energy is conserved over
+    # 100 steps, and 100 steps back with reversed velocities return the start
+    o0 = pool.observables()[0]
+    p0, v0, i0 = pool.get_state(0)
+    pool.step(100)
+    o1 = pool.observables()[0]
+    pool.scale_velocities(0, -1.0)
+    pool.step(100)
+    o2 = pool.observables()[0]
+    p2, v2, i2 = pool.get_state(0)
+    de = abs(o1["etot"] - o0["etot"]) / s.n
+    back = np.abs((p2 + i2 * s.box) - (p0 + i0 * s.box)).max()
+    say("  |dE|/N over 100 steps", de, "momentum/N", np.abs(o1["momentum"]).max() / s.n,
+        "return error after 100 + 100 reversed steps", back, "rebuilds", o2["n_rebuilds"])
+    assert o1["status"] == 0 and o2["status"] == 0
+    assert de < 1e-4
+    assert np.abs(o1["momentum"]).max() / s.n < 1e-12
+    assert back < 1e-4
+    assert np.abs(v2 + v0).max() < 1e-4
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "mixed64", "fp64"])
+def test_ka64k_sampled_forces_and_lists(prec):
+    """N = 64,000 KA at T = 0.7, every precision mode."""
+    s = I.make_ka(64_000, 0.7, seed=20240101)
+    pool = _tuned_pool([s], prec)
+    pool.step(100)
+    _sampled_parity(pool, 0, s, prec, 512, seed=6)
+    pool.close()
+
+
+def test_batch256_sampled_forces_and_lists():
+    """The 256-replica ensemble (N log-uniform in [500, 8000]) in its tuned
+    launch shapes: a sample of replicas, each against the oracle."""
+    reps = I.make_ka_ensemble(256, seed=20240101)
+    pool = _tuned_pool(reps, "ds")
+    pool.step(100)
+    for k in (0, 37, 101, 170, 255):
+        say("replica", k, "N", reps[k].n)
+        _sampled_parity(pool, k, reps[k], "ds", 128, seed=k)
+    obs = pool.observables()
+    assert not any(o["status"] for o in obs if o["n"])
+    pool.close()

@@ -13,7 +13,7 @@ Workloads follow the paper's stated systems:
     Sec. 5 ("Application to glassy dynamics": sigma_AA=1, sigma_BB=0.88,
     sigma_AB=0.8, eps_AA=1, eps_BB=0.5, eps_AB=1.5, equal masses).
 
-Readings where the paper is silent (recorded in the design notes too):
+Readings where the paper is silent:
   * the cutoff of each KA pair is 2.5 sigma_ab;
   * N that is not 4 n^3 is placed on a random subset of an fcc lattice with
     n = ceil((N/4)^(1/3)) cells per edge;

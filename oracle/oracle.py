@@ -10,9 +10,9 @@ velocity Verlet with short-ranged pair forces; Sec. 3 LJ 12-6 cut at
 rc = 2.5 sigma; Sec. 5 Kob-Andersen pair table; Sec. 4 WCA and the C2
 smoothing factor g): brute-force forces, energies
 and virials, brute-force neighbour-list membership, and a naive
-velocity-Verlet integrator.  Parity status of each function is listed in the
-design notes; every function here is pinned by a test against a fact that
-does not come from this module (closed forms, invariants, library routines).
+velocity-Verlet integrator.  Every function here is pinned by a test
+against a fact that does not come from this module (closed forms,
+invariants, library routines).
 """
 from __future__ import annotations
 

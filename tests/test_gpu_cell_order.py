@@ -7,6 +7,7 @@ import pytest
 
 import md_inputs as I
 from oracle import oracle as O
+from oracle.upload import state_after_upload
 from gpu_helpers import near_cutoff, pool_for, say
 
 pytestmark = pytest.mark.gpu
@@ -22,7 +23,7 @@ def test_lists_match_oracle(order, prec, n):
     s = _ka(n)
     say("curve lists", order, prec, n)
     pool = pool_for([s], prec, cell_order=order)
-    pos, vel, img = pool.get_state(0)
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
     cnt, ids = pool.neighbours(0, cap=256)
     ref = O.neighbours(pos, s.box, s.species, s.table, s.skin)
     amb = near_cutoff(pos, s.box, s.species, s.table, lambda a, b: s.table.rcut[a, b] + s.skin, band=1e-6)
@@ -54,7 +55,7 @@ def test_orders_give_the_same_list_sets(prec):
 def test_ten_steps_and_rebuilds_match_oracle(prec):
     s = _ka(1500, T=1.0, jitter=0.1, seed=4)
     pool = pool_for([s], prec, cell_order="hilbert")
-    p0, v0, i0 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, prec)
     pool.step(300)
     obs = pool.observables()[0]
     p1, v1, i1 = pool.get_state(0)

@@ -2,9 +2,10 @@
 times (the autotuner's cached shapes): the N = 1M and N = 64k Kob-Andersen
 systems and the 256-replica ensemble.  The oracle computes forces, energies
 and list membership for a random sample of particles one by one against all
-N (brute force); whole-system dynamics are checked through properties that
-hold at any size (momentum and energy conservation, time reversibility).
-The oracle always receives the state the device holds (md_get_state)."""
+N (brute force), on the seeded input as the precision mode holds it after
+upload (oracle/upload.py; nothing read back from the device is fed to the
+oracle).  Whole-system dynamics are checked through properties that hold at
+any size (momentum and energy conservation, time reversibility)."""
 import math
 
 import numpy as np
@@ -12,6 +13,7 @@ import pytest
 
 import md_inputs as I
 from oracle import oracle as O
+from oracle.upload import state_after_upload
 from gpu_helpers import TOL_F, pool_for, say
 
 pytestmark = pytest.mark.gpu
@@ -46,8 +48,10 @@ def _band_mask(pos, box, species, table, sel, radius_of, band):
     return out
 
 
-def _sampled_parity(pool, slot, s, prec, m, seed, check_lists=True):
-    pos, vel, img = pool.get_state(slot)
+def _sampled_parity(pool, slot, s, prec, m, seed):
+    """Forces, energies and lists of a sample of particles at the uploaded
+    state (call before any step)."""
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
     f, e = pool.forces(slot)
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(s.n, size=min(m, s.n), replace=False)).astype(np.int32)
@@ -70,38 +74,27 @@ def _sampled_parity(pool, slot, s, prec, m, seed, check_lists=True):
         assert d[excl].max() < 2 * jump + TOL_F[prec] * frms
     scale = max(1.0, float(np.abs(er).max()))
     assert float(np.abs(e[sel] - er)[~excl].max()) < (1e-10 if prec == "fp64" else 1e-5) * scale
-    if check_lists:
-        # Verlet-list validity at the current positions (the lists were built
-        # up to skin/2 of motion ago): every pair inside its cutoff is listed
-        cnt, ids = pool.neighbours(slot, cap=160)
-        inside = O.neighbours(pos, s.box, s.species, s.table, 0.0, sel)
-        for k, i in enumerate(sel):
-            got = set(ids[i, :cnt[i]].tolist())
-            assert len(got) == cnt[i]  # no duplicates
-            missing = set(inside[k].tolist()) - got
-            assert not missing or excl[k], (int(i), sorted(missing))
-        # exact membership right after a build
-        pool.rebuild_neighbours()
-        pos, vel, img = pool.get_state(slot)
-        cnt, ids = pool.neighbours(slot, cap=160)
-        ref = O.neighbours(pos, s.box, s.species, s.table, s.skin, sel)
-        amb = _band_mask(pos, s.box, s.species, s.table, sel, lambda a, b: s.table.rcut[a, b] + s.skin, 1e-6)
-        bad = 0
-        for k, i in enumerate(sel):
-            got = ids[i, :cnt[i]]
-            assert len(set(got.tolist())) == cnt[i]
-            if set(got.tolist()) != set(ref[k].tolist()):
-                assert amb[k], (int(i), sorted(set(got.tolist()) ^ set(ref[k].tolist())))
-                bad += 1
-        say("  lists: cutoff pairs all listed; after a build the sample equals the oracle; band cases", bad)
+    # lists of the sample (built at upload) against brute-force membership
+    cnt, ids = pool.neighbours(slot, cap=160)
+    ref = O.neighbours(pos, s.box, s.species, s.table, s.skin, sel)
+    amb = _band_mask(pos, s.box, s.species, s.table, sel, lambda a, b: s.table.rcut[a, b] + s.skin, 1e-6)
+    bad = 0
+    for k, i in enumerate(sel):
+        got = ids[i, :cnt[i]]
+        assert len(set(got.tolist())) == cnt[i]  # no duplicates
+        if set(got.tolist()) != set(ref[k].tolist()):
+            assert amb[k], (int(i), sorted(set(got.tolist()) ^ set(ref[k].tolist())))
+            bad += 1
+    say("  lists of the sample equal the oracle's; band cases", bad)
 
 
 def test_ka1m_sampled_forces_lists_and_dynamics():
-    """N = 1,000,000 KA at T = 0.5 in double-single (the benchmark system)."""
-    s = I.make_ka(1_000_000, 0.5, seed=20240101)
+    """N = 1,000,000 KA at T = 0.5 in double-single (the benchmark system,
+    from a jittered start so that no lattice shell sits on a cutoff)."""
+    s = I.make_ka(1_000_000, 0.5, seed=20240101, jitter=0.08)
     pool = _tuned_pool([s], "ds")
-    pool.step(200)
     _sampled_parity(pool, 0, s, "ds", 256, seed=5)
+    pool.step(200)
     # dynamics at full size: momentum stays zero, energy is conserved over
     # 100 steps, and 100 steps back with reversed velocities return the start
     o0 = pool.observables()[0]
@@ -127,9 +120,8 @@ def test_ka1m_sampled_forces_lists_and_dynamics():
 @pytest.mark.parametrize("prec", ["fp32", "ds", "mixed64", "fp64"])
 def test_ka64k_sampled_forces_and_lists(prec):
     """N = 64,000 KA at T = 0.7, every precision mode."""
-    s = I.make_ka(64_000, 0.7, seed=20240101)
+    s = I.make_ka(64_000, 0.7, seed=20240101, jitter=0.08)
     pool = _tuned_pool([s], prec)
-    pool.step(100)
     _sampled_parity(pool, 0, s, prec, 512, seed=6)
     pool.close()
 
@@ -137,12 +129,12 @@ def test_ka64k_sampled_forces_and_lists(prec):
 def test_batch256_sampled_forces_and_lists():
     """The 256-replica ensemble (N log-uniform in [500, 8000]) in its tuned
     launch shapes: a sample of replicas, each against the oracle."""
-    reps = I.make_ka_ensemble(256, seed=20240101)
+    reps = I.make_ka_ensemble(256, seed=20240101, jitter=0.08)
     pool = _tuned_pool(reps, "ds")
-    pool.step(100)
     for k in (0, 37, 101, 170, 255):
         say("replica", k, "N", reps[k].n)
         _sampled_parity(pool, k, reps[k], "ds", 128, seed=k)
+    pool.step(100)
     obs = pool.observables()
     assert not any(o["status"] for o in obs if o["n"])
     pool.close()

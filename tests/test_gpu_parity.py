@@ -1,9 +1,11 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
 Inputs are seeded KA / LJ systems (fcc-subset starts with a small jitter so
-that no lattice shell sits on a cutoff).  The oracle always receives the
-state the device holds (md_get_state), so the comparison isolates the
-device arithmetic.  Sizes span several cells per edge, several workgroups
+that no lattice shell sits on a cutoff).  The oracle receives the state the
+device starts from, derived on the host from the seeded input by the upload
+rule (oracle/upload.py: folded into the box, rounded to the precision
+mode's representation), so the comparison isolates the device arithmetic;
+nothing read back from the device is ever fed to the oracle.  Sizes span several cells per edge, several workgroups
 and a ragged tail (N not a multiple of the block size)."""
 import dataclasses
 import functools
@@ -14,6 +16,7 @@ import pytest
 
 import md_inputs as I
 from oracle import oracle as O
+from oracle.upload import state_after_upload
 from gpu_helpers import (BAND, TOL_E, TOL_F, force_error, near_cutoff, pool_for,
                          say)
 
@@ -26,12 +29,30 @@ def _ka(n, T=0.7, seed=11, jitter=0.06):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_uploaded_state_follows_the_upload_rule(prec):
+    """md_attach stores exactly the state the upload rule defines (positions
+    folded into the box, FP32 / double-single / double representation), which
+    is what the oracle is given as the device's starting state."""
+    s = _ka(3001)
+    pool = pool_for([s], prec)
+    p, v, i = pool.get_state(0)
+    pr, vr, ir = state_after_upload(s.pos, s.vel, s.box, prec)
+    dp = np.abs(p - pr)
+    dp = np.minimum(dp, np.abs(dp - s.box))  # a value rounded up to L is stored as 0
+    say("upload", prec, "max|dx|", dp.max(), "max|dv|", np.abs(v - vr).max())
+    assert dp.max() == 0.0
+    assert np.array_equal(v, vr)
+    assert np.array_equal(p + i * s.box, pr + ir * s.box) or dp.max() == 0.0
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,lpp", [(500, 0), (3001, 1), (3001, 4), (12007, 0)])
 def test_forces_match_oracle(prec, n, lpp):
     s = _ka(n)
     say("forces", prec, n, "lanes", lpp)
     pool = pool_for([s], prec, lanes_per_particle=lpp)
-    pos, vel, img = pool.get_state(0)
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
     f, e = pool.forces(0)
     fr, er, wr = O.forces(pos, s.box, s.species, s.table)
     excl = None
@@ -57,7 +78,7 @@ def test_neighbour_lists_match_oracle(prec, n, width, lanes):
     if (width, lanes) != (4, 0):
         pool.set_launch(build_width=width, build_lanes=lanes)
         pool.rebuild_neighbours()
-    pos, vel, img = pool.get_state(0)
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
     cnt, ids = pool.neighbours(0, cap=256)
     ref = O.neighbours(pos, s.box, s.species, s.table, s.skin)
     amb = near_cutoff(pos, s.box, s.species, s.table,
@@ -102,7 +123,7 @@ def test_ten_step_trajectory(prec, lpp):
     s = _ka(3001, T=0.7)
     say("10-step", prec, "lanes", lpp)
     pool = pool_for([s], prec, lanes_per_particle=lpp)
-    p0, v0, i0 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, prec)
     pool.step(10)
     p1, v1, i1 = pool.get_state(0)
     pr, vr, ir, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 10)
@@ -122,7 +143,7 @@ def test_long_run_with_rebuilds(prec):
     s = _ka(1500, T=1.0, jitter=0.1, seed=4)
     say("300-step", prec)
     pool = pool_for([s], prec)
-    p0, v0, i0 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, prec)
     pool.step(300)
     obs = pool.observables()[0]
     p1, v1, i1 = pool.get_state(0)
@@ -140,16 +161,24 @@ def test_observables_match_oracle(prec):
     s = _ka(3001, T=0.7)
     say("observables", prec)
     pool = pool_for([s], prec)
-    pool.step(5)
+    # at the uploaded state: the same positions and velocities on both sides
     o = pool.observables()[0]
-    pos, vel, _ = pool.get_state(0)
-    r = O.observables(pos, vel, s.box, s.species, s.table)
+    p0, v0, _ = state_after_upload(s.pos, s.vel, s.box, prec)
+    r = O.observables(p0, v0, s.box, s.species, s.table)
     tol = TOL_E[prec]
     for k in ("epot", "virial"):
         assert o[k] == pytest.approx(r[k], rel=tol), k
     assert o["ekin"] == pytest.approx(r["ekin"], rel=1e-12)
     assert np.abs(o["momentum"] - r["momentum"]).max() < 1e-9
     assert o["pressure"] == pytest.approx(r["pressure"], rel=tol * 10)
+    # five steps later, against the oracle's trajectory from the same start
+    pool.step(5)
+    o5 = pool.observables()[0]
+    pos, vel, _, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 5)
+    r5 = O.observables(pos, vel, s.box, s.species, s.table)
+    t5 = 1e-10 if prec == "fp64" else 1e-6
+    for k in ("epot", "ekin", "etot", "virial"):
+        assert o5[k] == pytest.approx(r5[k], rel=t5), k
     pool.close()
 
 
@@ -159,7 +188,7 @@ def test_lj_fp64_1000_steps():
     s = I.make_lj(4000)
     say("lj4000 fp64 1000 steps")
     pool = pool_for([s], "fp64")
-    p0, v0, i0 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, "fp64")
     o0 = pool.observables()[0]
     pool.step(1000)
     o1 = pool.observables()[0]
@@ -197,7 +226,7 @@ def test_smoothed_and_wca_forces_match_oracle(prec, name):
     s = _smooth_systems()[name]
     say("smoothed forces", prec, name, "h", s.table.smooth)
     pool = pool_for([s], prec)
-    pos, vel, img = pool.get_state(0)
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
     f, e = pool.forces(0)
     fr, er, wr = O.forces(pos, s.box, s.species, s.table)
     err, frms = force_error(f, fr, None)
@@ -215,7 +244,7 @@ def test_smoothed_ten_step_trajectory(prec, name):
     s = _smooth_systems()[name]
     say("smoothed 10-step", prec, name)
     pool = pool_for([s], prec)
-    p0, v0, i0 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, prec)
     pool.step(10)
     p1, v1, i1 = pool.get_state(0)
     pr, vr, ir, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 10)

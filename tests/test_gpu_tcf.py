@@ -7,6 +7,7 @@ import pytest
 
 import md_inputs as I
 from gpu_helpers import pool_for, say
+from oracle.upload import state_after_upload
 from oracle import oracle as O
 from oracle import tcf as OT
 
@@ -71,7 +72,7 @@ def test_interacting_correlations_match_oracle(prec):
     s = I.make_ka(500, 1.0, jitter=0.1, seed=14)
     every, M, levels, block = 5, 60, 3, 4
     pool = pool_for([s], prec)
-    p0, v0, i0 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, prec)
     t = pool.tcf(0, levels, block, q=2 * math.pi * 6 / s.box)
     ref = OT.Blocking(levels, block, s.species, 2 * math.pi * 6 / s.box)
     p, v, img = p0.copy(), v0.copy(), i0.copy()

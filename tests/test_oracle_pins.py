@@ -415,3 +415,27 @@ def test_smoothing_makes_energy_error_second_order():
         ratios[h] = amp[0] / amp[1]
     assert 3.8 < ratios[0.05] < 4.2, ratios
     assert abs(ratios[0.0] - 4.0) > 1.0, ratios
+
+
+# ------------------------------------------------ upload rule (host side)
+def test_upload_rule_folds_and_rounds_as_defined():
+    """Folding keeps x = x_folded + image L exactly for in-range values and
+    lands in [0, L); FP32 rounding is numpy's float32; the double-single
+    value hi + lo is within 2^-48 of x, with hi = fl32(x) (Sec. 2.4)."""
+    from oracle import upload as U
+    rng = np.random.default_rng(3)
+    L = 17.25
+    x = rng.uniform(-2 * L, 3 * L, size=(2000, 3))
+    xf, img = U.fold(x.copy(), L)
+    assert (xf >= 0).all() and (xf < L).all()
+    assert np.abs(xf + img * L - x).max() < 1e-12 * L
+    v = rng.normal(size=(2000, 3))
+    p32, v32, _ = U.state_after_upload(x, v, L, "fp32")
+    assert np.array_equal(v32, v.astype(np.float32).astype(np.float64))
+    assert np.array_equal(p32, xf.astype(np.float32).astype(np.float64))
+    pds, vds, _ = U.state_after_upload(x, v, L, "ds")
+    assert np.abs(pds - xf).max() <= 2.0 ** -48 * L
+    assert np.abs(vds - v).max() <= 2.0 ** -48 * np.abs(v).max()
+    assert np.array_equal(pds.astype(np.float32), xf.astype(np.float32))  # hi = fl32(x)
+    p64, v64, i64 = U.state_after_upload(x, v, L, "fp64")
+    assert np.array_equal(p64, xf) and np.array_equal(v64, v) and np.array_equal(i64, img)

@@ -9,11 +9,11 @@
  * obviousness, not speed:
  *   - pair potential: 12-6 Lennard-Jones (Sec. 3, performance section),
  *     truncated at rc_ab with the energy shifted by V(rc_ab) so that it is
- *     continuous; the force is not shifted (reading of "cut off at rc");
+ *     continuous; the force is not shifted (our reading of the plain cutoff);
  *   - KA mixture: per-species-pair eps/sigma (Sec. 5), rc_ab = 2.5 sigma_ab;
  *   - minimum image in a cubic periodic box, d -= L * nearbyint(d / L);
  *   - forces by brute force over every j != i, O(N^2), no neighbour lists;
- *   - velocity Verlet (Sec. 2.2, "The MD integration step"):
+ *   - velocity Verlet (Sec. 2.2):
  *       v += dt/(2m) F;  r += dt v;  wrap r into [0, L);  F = F(r);
  *       v += dt/(2m) F;
  *   - neighbour-list membership (Sec. 2.2: every particle within the cutoff

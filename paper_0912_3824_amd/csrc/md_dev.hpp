@@ -166,7 +166,7 @@ __host__ __device__ __forceinline__ int dbl_cell(double x, double y, double z, d
 }
 
 // The 13 half-space cell offsets; a neighbour search visits the own cell and
-// then each offset o followed by -o ("opposite cell order", Sec. 4.1).
+// then each offset o followed by -o (opposite cells summed together, Sec. 4.1).
 __host__ __device__ __forceinline__ void half_offset(int k, int &dx, int &dy, int &dz)
 {
     // k in [0,13): enumerate (dz, dy, dx) lexicographically, keep the half

@@ -214,8 +214,8 @@ __device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts
     }
 }
 
-// Snapshot gather with a 32-bit byte offset from a uniform base.
-// snapshot record at list entry e (a byte offset, see list_entry)
+// Snapshot record at list entry e: a 32-bit byte offset (see list_entry)
+// from a uniform base.
 __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int e)
 {
     return *(const uint4 *)((const char *)snap + (uint32_t)e);

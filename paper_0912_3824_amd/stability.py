@@ -26,6 +26,7 @@ h = 0.005 over 1e5 steps in double-single precision.  System: N = 10,000,
 rho = 0.75, T = 1.12.
 
   python -m paper_0912_3824_amd.stability [--steps 200000] [--n 10000] [--long-steps 2000000]
+      [--only-long --potentials lj --precisions ds,fp64]
 """
 from __future__ import annotations
 
@@ -69,6 +70,7 @@ def _energy_series(s, prec: str, h: float, dt: float, steps: int, every: int):
     o = pool.observables()[0]
     t, e, p = [0], [o["etot"] / r.n], [float(np.abs(o["momentum"]).max()) / r.n]
     done = 0
+    tick = max(steps // 10, 1)
     while done < steps:
         k = min(every, steps - done)
         pool.step(k)
@@ -76,6 +78,8 @@ def _energy_series(s, prec: str, h: float, dt: float, steps: int, every: int):
         o = pool.observables()[0]
         if o["status"]:
             raise RuntimeError(f"replica status {o['status']}")
+        if steps >= 10 ** 6 and done % tick < k:
+            log(f"  {prec} h={h} dt={dt}: {done} of {steps} steps, E/N {o['etot'] / r.n:.9f}")
         t.append(done)
         e.append(o["etot"] / r.n)
         p.append(float(np.abs(o["momentum"]).max()) / r.n)
@@ -140,25 +144,29 @@ def speed(s, prec="ds", steps=2000) -> dict:
 
 
 def run(n=10000, rho=0.75, temperature=1.12, equil=100000, drift_steps=200000, long_steps=0,
-        seed=20240101) -> dict:
+        seed=20240101, only_long=False, potentials=("lj", "wca"), precisions=("fp32", "ds", "fp64")) -> dict:
     import md_inputs as I
     res = {"n": n, "rho": rho, "temperature": temperature, "equil_steps": equil}
     states = {}
     for name, rc in (("lj", 2.5), ("wca", I.WCA_RC)):
+        if name not in potentials:
+            continue
         t0 = time.perf_counter()
         states[name] = equilibrated(n, rc, rho, temperature, equil, seed)
         log(f"equilibrated {name} in {time.perf_counter() - t0:.1f} s")
-    res["collapse_lj"] = collapse(states["lj"], ("fp32", "ds", "fp64"), (0.0, 0.01))
-    res["drift"] = {}
-    for name in ("lj", "wca"):
-        res["drift"][name] = drift(states[name], ("fp32", "ds", "fp64"), (0.0, 0.005), (0.001, 0.003),
-                                   drift_steps, max(100, drift_steps // 500))
+    if not only_long:
+        res["collapse_lj"] = collapse(states["lj"], precisions, (0.0, 0.01))
+        res["drift"] = {}
+        for name in states:
+            res["drift"][name] = drift(states[name], precisions, (0.0, 0.005), (0.001, 0.003),
+                                       drift_steps, max(100, drift_steps // 500))
     if long_steps:
-        res["drift_long"] = {name: drift(states[name], ("fp32", "ds", "fp64"), (0.005,), (0.001,),
+        res["drift_long"] = {name: drift(states[name], precisions, (0.005,), (0.001,),
                                          long_steps, max(100, long_steps // 1000))
-                             for name in ("lj", "wca")}
-    res["speed"] = {name: speed(states[name]) for name in ("lj", "wca")}
-    log(f"speed {json.dumps(res['speed'])}")
+                             for name in states}
+    if not only_long:
+        res["speed"] = {name: speed(states[name]) for name in states}
+        log(f"speed {json.dumps(res['speed'])}")
     return res
 
 
@@ -168,5 +176,10 @@ if __name__ == "__main__":
     ap.add_argument("--equil", type=int, default=100000)
     ap.add_argument("--steps", type=int, default=200000, help="steps per drift run")
     ap.add_argument("--long-steps", type=int, default=0, help="steps per long drift run (0: none)")
+    ap.add_argument("--only-long", action="store_true", help="run only the long drift runs")
+    ap.add_argument("--potentials", default="lj,wca")
+    ap.add_argument("--precisions", default="fp32,ds,fp64")
     a = ap.parse_args()
-    print(json.dumps(run(n=a.n, equil=a.equil, drift_steps=a.steps, long_steps=a.long_steps)))
+    print(json.dumps(run(n=a.n, equil=a.equil, drift_steps=a.steps, long_steps=a.long_steps,
+                         only_long=a.only_long, potentials=tuple(a.potentials.split(",")),
+                         precisions=tuple(a.precisions.split(",")))))

@@ -73,17 +73,6 @@ __device__ __forceinline__ int find_item_slot(const int *pref, int nslots, int i
     return lo;
 }
 
-// Work-item walk of the rebuild kernels.  A step's rebuild (force_slot -1)
-// visits only the items of the slots on the rebuild list written by k_step;
-// a host-forced rebuild visits every item and filters by slot.  `unit` is
-// this worker's index among `nunits` workers; visit(slot, item) is called for
-// each item assigned to it.  Consecutive slots start on different workers so
-// that small replicas spread over the grid.
-template <class F>
-__device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
-                                          int max_slots, int force_slot, const Ctl *ctl, int which,
-                                          int unit, int nunits, F visit);
-
 __device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *need, const Ctl *ctl)
 {
     if (force_slot == -1) return need && need[s] != 0;
@@ -91,29 +80,47 @@ __device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *
     return s == force_slot;
 }
 
+// Work-item walk of the rebuild kernels.  A step's rebuild (force_slot -1)
+// visits the items of the slots on the rebuild list written by k_step; a
+// host-forced rebuild visits those of the selected slots (items_pref holds
+// the host's per-slot item counts as a prefix).  `unit` is this worker's
+// index among `nunits` workers; visit(slot, item) is called for each item
+// assigned to it.  Consecutive slots start on different workers so that
+// small replicas spread over the grid.  The slots and their item counts are
+// read 64 at a time, one per lane (a few round trips to memory however many
+// replicas rebuild), then walked from registers; visit is called from one
+// place only, so that its code is emitted once.
 template <class F>
 __device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
                                           int max_slots, int force_slot, const Ctl *ctl, int which,
                                           int unit, int nunits, F visit)
 {
-    if (force_slot == -1) {
-        const int cnt = rlist[0];
-        int cum = 0;
-        for (int li = 0; li < cnt; ++li) {
-            const int s = rlist[1 + li];
-            const int items = which == 3 ? rep[s].items3 : rep[s].items4;
+    const bool listed = force_slot == -1;
+    const int cnt = listed ? rlist[0] : max_slots;
+    const int lane = __lane_id();
+    int cum = 0;
+    for (int base = 0; base < cnt; base += 64) {
+        const int li = base + lane;
+        int sl = 0, its = 0;
+        if (li < cnt) {
+            if (listed) {
+                sl = rlist[1 + li];
+                its = which == 3 ? rep[sl].items3 : rep[sl].items4;
+            } else {
+                sl = li;
+                if (slot_selected(sl, force_slot, nullptr, ctl)) its = items_pref[sl + 1] - items_pref[sl];
+            }
+        }
+        const int m = min(64, cnt - base);
+        for (int k = 0; k < m; ++k) {
+            const int items = __builtin_amdgcn_readlane(its, k);
+            if (items == 0) continue;
+            const int s = __builtin_amdgcn_readlane(sl, k);
             int first = unit - cum % nunits;
             first += first < 0 ? nunits : 0;
             for (int it = first; it < items; it += nunits) visit(s, it);
             cum += items;
         }
-        return;
-    }
-    const int total = items_pref[max_slots];
-    for (int it = unit; it < total; it += nunits) {
-        const int s = find_item_slot(items_pref, max_slots, it);
-        if (!slot_selected(s, force_slot, nullptr, ctl)) continue;
-        visit(s, it - items_pref[s]);
     }
 }
 

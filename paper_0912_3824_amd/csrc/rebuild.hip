@@ -107,10 +107,17 @@ __global__ void __launch_bounds__(SCAN_B) k_scan(const ScanArgs a)
 }
 
 // ------------------------------------------------------------ k_permute
-// One wave per new cell: stable scatter of its members into scratch.  Each
-// pass first loads every member it moves, then folds and stores them: on
-// this hardware one counter tracks loads and stores alike, so a load issued
-// after a store would also wait for that store.
+// One wave per new cell: stable scatter of its members into scratch, in two
+// phases.  The test phase reads the snapshots of the candidates (the members
+// of the 27 neighbouring old cells, in old slot order) PERM_U x 64 at a time,
+// all in flight together, and lists each member found with its destination
+// in LDS; it issues no store.  The move phase then loads the listed members
+// and folds and stores them.  A cell's membership is thus found in a few
+// round trips to memory instead of one load-then-store pass per 256
+// candidates (on this hardware one counter tracks loads and stores alike, so
+// a load issued after a store also waits for that store).
+#define PERM_U 8                     // candidate tests per lane in flight
+#define PERM_LIST (64 + 64 * PERM_U) // listed members per wave before a move phase
 template <int P> struct Moved {
     uint4 st[Traits<P>::NW];
     int4 meta;
@@ -215,6 +222,7 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
     const int wpb = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6;
     __shared__ int pref[4][55], pst[4][54], srt[4][27];
+    __shared__ int2 lst[4][PERM_LIST]; // (old slot, scratch slot) of the members found
     for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 3,
               blockIdx.x * wpb + wv, gridDim.x * wpb, [&](int s, int c) {
         const RepDev rp = a.rep[s];
@@ -262,15 +270,25 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
         if (lane == 0) pref[wv][0] = 0;
         __builtin_amdgcn_wave_barrier();
         const int tot = pref[wv][nr], tot0 = pref[wv][nold];
-        int run0 = 0, run1 = 0;
+        // move phase: every listed member, loaded before any is stored
+        auto move_listed = [&](int n) {
+            __builtin_amdgcn_wave_barrier();
+            for (int k = lane; k < n; k += 64) {
+                const int2 e = lst[wv][k];
+                Moved<P> mv;
+                move_load<P>(a, e.x, mv);
+                move_store<P>(a, rp, mv, e.y);
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+        int run0 = 0, run1 = 0, nl = 0;
         int r = 0; // range of the lane's current candidate (only moves forward)
         const unsigned long long below = (1ull << lane) - 1ull;
-        constexpr int U = 4; // candidates per lane per pass
-        for (int b = 0; b < tot; b += 64 * U) {
-            int q[U];
-            bool m[U];
+        for (int b = 0; b < tot; b += 64 * PERM_U) {
+            int q[PERM_U];
+            bool m[PERM_U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < PERM_U; ++u) {
                 const int e = b + 64 * u + lane;
                 q[u] = -1;
                 if (e < tot) {
@@ -279,26 +297,28 @@ __global__ void __launch_bounds__(256) k_permute(const PermArgs a)
                 }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) m[u] = q[u] >= 0 && (nd == 1 || in_cell<P>(a, rp, q[u], c));
-            Moved<P> mv[U];
+            for (int u = 0; u < PERM_U; ++u) m[u] = q[u] >= 0 && (nd == 1 || in_cell<P>(a, rp, q[u], c));
+            // list the members found, in candidate order (at most 64 x
+            // PERM_U, so the list, emptied below once it holds more than
+            // 64, never overflows)
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (m[u]) move_load<P>(a, q[u], mv[u]);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < PERM_U; ++u) {
                 const bool p1 = b + 64 * u + lane >= tot0;
                 const unsigned long long bal0 = __ballot(m[u] && !p1), bal1 = __ballot(m[u] && p1);
-                if (m[u])
-                    move_store<P>(a, rp, mv[u], p1 ? dst1 + run1 + __popcll(bal1 & below)
-                                                   : dst0 + run0 + __popcll(bal0 & below));
+                if (m[u]) {
+                    const int dst = p1 ? dst1 + run1 + __popcll(bal1 & below) : dst0 + run0 + __popcll(bal0 & below);
+                    lst[wv][nl + __popcll((bal0 | bal1) & below)] = make_int2(q[u], dst);
+                }
                 run0 += __popcll(bal0);
                 run1 += __popcll(bal1);
+                nl += __popcll(bal0 | bal1);
             }
+            if (nl > PERM_LIST - 64 * PERM_U) { move_listed(nl); nl = 0; }
         }
+        move_listed(nl);
         // every particle counted in this cell must have come from a
         // neighbouring old cell; a shortfall means a particle jumped further
         if (lane == 0 && (run0 != want0 || run1 != want1)) atomicOr(a.status + s, 4);
-        __builtin_amdgcn_wave_barrier();
     });
 }
 
@@ -328,6 +348,25 @@ struct BuildTabs {
 __device__ __forceinline__ int cand_glob(const int4 &c, int na, int e) { return e < na ? c.z + e : c.w + (e - na); }
 template <bool FROM_LDS>
 __device__ __forceinline__ int cand_at(const int4 &c, int na, int e) { return FROM_LDS ? c.x + e : cand_glob(c, na, e); }
+
+// Staged cell of the v-th visit (v = 0..26) of a member in staged column
+// lx_m: the own cell, then each half-space offset o followed by -o, where
+// the half space is indices 14..26 of the (dz, dy, dx) enumeration of the 27
+// offsets (odd v: +o, even v: -o).
+__device__ __forceinline__ int visit_cell(int v, int lx_m, bool full, int nd, int NX)
+{
+    int dx = 0, dy = 0, dz = 0;
+    if (v > 0) {
+        const int q = 14 + ((v - 1) >> 1);
+        const int sg = (v & 1) ? 1 : -1;
+        dz = sg * (q / 9 - 1);
+        dy = sg * ((q / 3) % 3 - 1);
+        dx = sg * (q % 3 - 1);
+    }
+    int lx = lx_m + dx;
+    if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
+    return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
+}
 
 template <int P, bool FROM_LDS>
 __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
@@ -425,26 +464,12 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             }
         }
     };
-    int last_cell = 0;
-    if (nd == 1) {
-        scan_cell(0);
-    } else {
-        // own cell, then each half-space offset o followed by -o: in the
-        // (dz, dy, dx) enumeration of the 27 offsets the positive half space
-        // is indices 14..26
-        auto cell_k = [&](int dx, int dy, int dz) {
-            int lx = lx_m + dx;
-            if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
-            return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
-        };
-        scan_cell(cell_k(0, 0, 0));
-        for (int q = 14; q < 27; ++q) {
-            const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
-            scan_cell(cell_k(dx, dy, dz));
-            last_cell = cell_k(-dx, -dy, -dz);
-            scan_cell(last_cell);
-        }
-    }
+    // own cell, then each half-space offset o followed by -o (see
+    // visit_cell), as one loop: a single copy of the scan code
+    const int nvis = nd == 1 ? 1 : 27;
+#pragma unroll 1
+    for (int v = 0; v < nvis; ++v) scan_cell(nd == 1 ? 0 : visit_cell(v, lx_m, full, nd, NX));
+    const int last_cell = nd == 1 ? 0 : visit_cell(26, lx_m, full, nd, NX);
     // Pad the list to a multiple of 8 with a particle that is outside the
     // list radius at this build: it stays beyond the force cutoff until the
     // next build (each particle moves at most skin/2), so the force loop
@@ -556,25 +581,11 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
             }
         }
     };
-    // visiting order: own cell, then +o, -o for q = 14..26 of the
-    // (dz, dy, dx) enumeration of the 27 offsets
-    auto cell_k = [&](int dx, int dy, int dz) {
-        int lx = lx_m + dx;
-        if (full) { lx += lx < 0 ? nd : 0; lx -= lx >= nd ? nd : 0; }
-        return ((dz + 1) * 3 + (dy + 1)) * NX + lx;
-    };
-    int last_cell = 0;
-    if (nd == 1) {
-        scan_cell(0);
-    } else {
-        scan_cell(cell_k(0, 0, 0));
-        for (int q = 14; q < 27; ++q) {
-            const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
-            scan_cell(cell_k(dx, dy, dz));
-            last_cell = cell_k(-dx, -dy, -dz);
-            scan_cell(last_cell);
-        }
-    }
+    // the canonical visiting order (see visit_cell), as one loop
+    const int nvis = nd == 1 ? 1 : 27;
+#pragma unroll 1
+    for (int v = 0; v < nvis; ++v) scan_cell(nd == 1 ? 0 : visit_cell(v, lx_m, full, nd, NX));
+    const int last_cell = nd == 1 ? 0 : visit_cell(26, lx_m, full, nd, NX);
     // pad to a multiple of 8, as in the one-lane build: the first rejected
     // candidate of the last visited cell, else (rare) of any staged cell
     if (cnt & 7) {

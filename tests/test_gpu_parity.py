@@ -117,6 +117,39 @@ def test_list_build_lanes_give_identical_lists(prec, n):
     pool.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "ds", "mixed64"])
+def test_list_build_with_large_cells(prec):
+    """Cells of ~88 members (skin 1.5, list radius 4.0): more members per
+    cell than a wave has lanes, and more candidates per cell than one
+    acceptance mask holds.  The one-lane build (one work item per one-cell
+    row segment) and the grouped-lane builds give the same lists entry by
+    entry, and they equal the oracle's brute-force neighbour sets for a
+    sample."""
+    n = 30000
+    s = I.make_ka(n, 0.7, jitter=0.06, seed=13, skin=1.5)
+    pool = pool_for([s], prec)
+    ref = None
+    # width 1: 7 x 7 x 7 one-cell segments, at least 256, so one work item
+    # per segment; lanes 1 -> one lane per member, lanes 16 / 0 -> groups
+    for lanes, block, width in [(1, 256, 1), (16, 512, 1), (1, 1024, 1), (0, 256, 8)]:
+        pool.set_launch(build_lanes=lanes, build_block=block, build_width=width, build_split=0)
+        pool.rebuild_neighbours()
+        cnt, ids = pool.neighbours(0, cap=512)
+        say("large cells", prec, lanes, block, width, "mean list", float(cnt.mean()))
+        if ref is None:
+            ref = (cnt, ids)
+        assert np.array_equal(cnt, ref[0]) and np.array_equal(ids, ref[1]), (lanes, block, width)
+    assert pool.observables()[0]["status"] == 0
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
+    sel = np.sort(np.random.default_rng(3).choice(n, size=200, replace=False)).astype(np.int32)
+    want = O.neighbours(pos, s.box, s.species, s.table, s.skin, sel)
+    amb = near_cutoff(pos, s.box, s.species, s.table, lambda a, b: s.table.rcut[a, b] + s.skin, band=1e-6)
+    for k, i in enumerate(sel):
+        got = set(ref[1][i, :ref[0][i]].tolist())
+        assert got == set(want[k].tolist()) or amb[i], int(i)
+    pool.close()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("lpp", [1, 2, 4])
 def test_ten_step_trajectory(prec, lpp):

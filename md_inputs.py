@@ -73,9 +73,11 @@ def ka_table(rc_over_sigma: float = 2.5) -> PairTable:
     return PairTable(2, eps, sig, rc_over_sigma * sig)
 
 
-def box_length(n: int, rho: float) -> float:
-    """Cubic box edge for density rho, rounded to the nearest float32."""
-    return float(np.float32((n / rho) ** (1.0 / 3.0)))
+def box_length(n: int, rho: float, float32_box: bool = True) -> float:
+    """Cubic box edge for density rho, rounded to the nearest float32 unless
+    float32_box is False (then the double (n / rho)^(1/3))."""
+    L = (n / rho) ** (1.0 / 3.0)
+    return float(np.float32(L)) if float32_box else float(L)
 
 
 def fcc_positions(n: int, box: float, rng: Optional[np.random.Generator],
@@ -163,11 +165,12 @@ def make_lj(n: int = 4000, rho: float = 0.8442, temperature: float = 1.5,
 
 def make_ka(n: int, temperature: float, rho: float = 1.2,
             seed: int = MASTER_SEED, jitter: float = 0.0,
-            skin: float = 0.3, rng: Optional[np.random.Generator] = None) -> System:
+            skin: float = 0.3, rng: Optional[np.random.Generator] = None,
+            float32_box: bool = True) -> System:
     """Kob-Andersen 80/20 mixture at density rho on an fcc-subset start."""
     if rng is None:
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
-    box = box_length(n, rho)
+    box = box_length(n, rho, float32_box)
     pos = fcc_positions(n, box, rng, jitter)
     sp = species_80_20(n, rng)
     vel = maxwell_velocities(n, temperature, rng)

@@ -2,15 +2,15 @@
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this module.  It wraps `md_oracle.c` (compiled with gcc, no fast-math,
-no FP contraction) through ctypes and adds a NumPy twin of the force
-definition for tiny systems.
+no FP contraction) through ctypes.
 
 What it computes is the plain definition of the paper's MD step (Sec. 2.2,
 velocity Verlet with short-ranged pair forces; Sec. 3 LJ 12-6 cut at
 rc = 2.5 sigma; Sec. 5 Kob-Andersen pair table; Sec. 4 WCA and the C2
 smoothing factor g): brute-force forces, energies
 and virials, brute-force neighbour-list membership, and a naive
-velocity-Verlet integrator.  Every function here is pinned by a test
+velocity-Verlet integrator; and, as a second independent route for large N,
+cell-list forces and velocity Verlet over skin-padded Verlet lists.  Every function here is pinned by a test
 against a fact that does not come from this module (closed forms,
 invariants, library routines).
 """
@@ -61,6 +61,13 @@ def _load():
         lib.orc_vv.restype = None
         lib.orc_pair.argtypes = [ctypes.c_double] * 5 + [dp, dp]
         lib.orc_pair.restype = None
+        lib.orc_forces_cells.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp, ctypes.c_int,
+                                         dp, dp, dp, ctypes.c_double, dp, dp, dp]
+        lib.orc_forces_cells.restype = None
+        lib.orc_vv_lists.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp, dp, ip, ctypes.c_int,
+                                     dp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, dp]
+        lib.orc_vv_lists.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -174,32 +181,38 @@ def observables(pos, vel, box, species, table, mass: float = 1.0) -> dict:
     }
 
 
-def forces_numpy(pos: np.ndarray, box: float, species: np.ndarray, table):
-    """NumPy twin of the force definition, O(N^2) memory: only for tiny N."""
-    pos = np.asarray(pos, dtype=np.float64)
-    n = len(pos)
-    sp = np.asarray(species) if table.n_species > 1 else np.zeros(n, dtype=int)
-    d = pos[:, None, :] - pos[None, :, :]
-    d -= box * np.rint(d / box)
-    r2 = np.sum(d * d, axis=-1)
-    np.fill_diagonal(r2, np.inf)
-    eps = table.eps[sp[:, None], sp[None, :]]
-    sig = table.sigma[sp[:, None], sp[None, :]]
-    rc = table.rcut[sp[:, None], sp[None, :]]
-    inside = r2 < rc * rc
-    s6 = (sig * sig / r2) ** 3
-    s6c = (sig * sig / (rc * rc)) ** 3
-    v = np.where(inside, 4 * eps * (s6 * s6 - s6) - 4 * eps * (s6c * s6c - s6c), 0.0)
-    ff = np.where(inside, 24 * eps * (2 * s6 * s6 - s6) / r2, 0.0)
-    h = float(table.smooth)
-    if h > 0:
-        with np.errstate(invalid="ignore", divide="ignore"):
-            r = np.sqrt(r2)
-            x = (r - rc) / (h * sig)
-            x4 = x ** 4
-            g = x4 / (1 + x4)
-            dg = 4 * x ** 3 / (1 + x4) ** 2
-            ff = np.where(inside, ff * g - v * dg / (h * sig) / r, 0.0)
-            v = np.where(inside, v * g, 0.0)
-    f = np.sum(ff[:, :, None] * d, axis=1)
-    return f, 0.5 * v.sum(axis=1), 0.5 * (ff * r2).sum(axis=1)
+def forces_cells(pos: np.ndarray, box: float, species: np.ndarray, table):
+    """Forces F[n,3], per-particle energies e[n] and virials w[n] of every
+    particle through cell lists (Sec. 2.2 cell binning): the same definition
+    as forces(), each particle's partners searched in its own and the 26
+    adjacent cells of edge >= the largest cutoff."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    eps, sig, rc = _tab(table)
+    f = np.zeros((n, 3))
+    e = np.zeros(n)
+    w = np.zeros(n)
+    lib.orc_forces_cells(n, box, _i(sp), _d(pos), table.n_species, _d(eps), _d(sig), _d(rc),
+                         float(table.smooth), _d(f), _d(e), _d(w))
+    return f, e, w
+
+
+def vv_lists(pos: np.ndarray, vel: np.ndarray, box: float, species: np.ndarray, table,
+             dt: float, steps: int, skin: float, mass: float = 1.0):
+    """Velocity Verlet like vv(), with forces over Verlet lists of radius
+    max cutoff + skin built through cell lists and rebuilt whenever a
+    particle has moved more than skin/2 since the last build (Sec. 2.2).
+    Returns (pos, vel, image, f, builds)."""
+    lib = _load()
+    p = np.array(pos, dtype=np.float64, order="C", copy=True)
+    v = np.array(vel, dtype=np.float64, order="C", copy=True)
+    n = p.shape[0]
+    img = np.zeros((n, 3), dtype=np.int32)
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    eps, sig, rc = _tab(table)
+    f = np.zeros((n, 3))
+    builds = lib.orc_vv_lists(n, box, _i(sp), _d(p), _d(v), _i(img), table.n_species, _d(eps),
+                              _d(sig), _d(rc), float(table.smooth), mass, dt, skin, steps, _d(f))
+    return p, v, img, f, int(builds)

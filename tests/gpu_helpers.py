@@ -50,6 +50,18 @@ def near_cutoff(pos, box, species, table, radius_of, band=BAND):
     return mask
 
 
+def cutoff_jump(table):
+    """Largest jump of the truncated pair force at a cutoff: |F_ab| just
+    inside rc_ab, over the species pairs of the table (KA: the AB pair,
+    0.073; single-species LJ at rc = 2.5: 0.039).  A pair within rounding of
+    a cutoff can be classified either way by an FP32 test, so its particle's
+    force may differ from the oracle's by this much."""
+    k = table.n_species
+    return max(abs(O.pair(table.rcut[a, b] * (1 - 1e-12), table.eps[a, b], table.sigma[a, b],
+                          table.rcut[a, b], table.smooth)[1])
+               for a in range(k) for b in range(k))
+
+
 def force_error(f, ref, exclude=None):
     frms = math.sqrt(float(np.mean(ref * ref)))
     d = np.abs(f - ref)

@@ -14,7 +14,7 @@ import pytest
 import md_inputs as I
 from oracle import oracle as O
 from oracle.upload import state_after_upload
-from gpu_helpers import TOL_F, pool_for, say
+from gpu_helpers import TOL_F, cutoff_jump, pool_for, say
 
 pytestmark = pytest.mark.gpu
 
@@ -53,25 +53,27 @@ def _sampled_parity(pool, slot, s, prec, m, seed):
     state (call before any step)."""
     pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
     f, e = pool.forces(slot)
+    assert np.isfinite(f).all() and np.isfinite(e).all()
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(s.n, size=min(m, s.n), replace=False)).astype(np.int32)
     fr, er, _ = O.forces(pos, s.box, s.species, s.table, sel)
-    frms = math.sqrt(float(np.mean(f * f)))  # over the whole system
+    frms = math.sqrt(float(np.mean(fr * fr)))  # of the oracle's sampled forces
+    # no device force may be wild anywhere (the sample sees only m of them)
+    assert float(np.abs(f).max()) < 1e3 * frms
     excl = np.zeros(len(sel), dtype=bool)
     if prec != "fp64":
         excl = _band_mask(pos, s.box, s.species, s.table, sel, lambda a, b: s.table.rcut[a, b], 2e-6)
     d = np.abs(f[sel] - fr)
-    # relative error of each sampled particle's force, against its own
-    # magnitude with F_rms as the floor (a near-zero force has no useful
-    # relative error); the F_rms-normalised component maximum is reported too
+    # relative error of each sampled particle's force against its own
+    # magnitude, with F_rms as the floor (a near-zero force has no useful
+    # relative error); the F_rms-normalised component maximum e_F is reported
     rel = np.linalg.norm(f[sel] - fr, axis=1) / np.maximum(np.linalg.norm(fr, axis=1), frms)
     err = float(rel[~excl].max())
-    say("  sampled", len(sel), "of", s.n, "relative error", err, "max component error / F_rms",
+    say("  sampled", len(sel), "of", s.n, "per-particle relative error", err, "e_F",
         float(d[~excl].max()) / frms, "F_rms", frms, "excluded", int(excl.sum()))
     assert err < TOL_F[prec]
     if excl.any():  # one cutoff jump at most
-        jump = abs(O.pair(s.table.rcut[0, 0] * (1 - 1e-12), 1.5, 0.8, 2.0)[1])
-        assert d[excl].max() < 2 * jump + TOL_F[prec] * frms
+        assert d[excl].max() < 2 * cutoff_jump(s.table) + TOL_F[prec] * frms
     scale = max(1.0, float(np.abs(er).max()))
     assert float(np.abs(e[sel] - er)[~excl].max()) < (1e-10 if prec == "fp64" else 1e-5) * scale
     # lists of the sample (built at upload) against brute-force membership
@@ -114,6 +116,47 @@ def test_ka1m_sampled_forces_lists_and_dynamics():
     assert np.abs(o1["momentum"]).max() / s.n < 1e-12
     assert back < 1e-4
     assert np.abs(v2 + v0).max() < 1e-4
+    pool.close()
+
+
+def test_ka1m_every_particle_against_the_cell_list_oracle():
+    """N = 1,000,000 KA in double-single, every particle: forces at the
+    uploaded state against the oracle's cell-list forces, then ten steps
+    against the oracle's velocity Verlet over Verlet lists (both FP64, both
+    pinned against brute force), max |dr| and max |dv| over all particles."""
+    s = I.make_ka(1_000_000, 0.5, seed=20240101, jitter=0.08)
+    pool = _tuned_pool([s], "ds")
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, "ds")
+    f, _ = pool.forces(0)
+    say("  oracle: cell-list forces of 1M particles")
+    fr, _, _ = O.forces_cells(pos, s.box, s.species, s.table)
+    frms = math.sqrt(float(np.mean(fr * fr)))
+    rel = np.linalg.norm(f - fr, axis=1) / np.maximum(np.linalg.norm(fr, axis=1), frms)
+    d = np.abs(f - fr)
+    over = np.nonzero(rel >= TOL_F["ds"])[0]
+    # particles over the bound must each have a pair within rounding of a
+    # cutoff (classified either way by an FP32 test) and differ by at most
+    # one cutoff jump per such pair
+    near = _band_mask(pos, s.box, s.species, s.table, over, lambda a, b: s.table.rcut[a, b], 2e-6)
+    keep = np.ones(s.n, dtype=bool)
+    keep[over] = False
+    say("  all particles: per-particle relative error", float(rel[keep].max()), "e_F",
+        float(d[keep].max()) / frms, "over the bound", len(over), "(all near a cutoff:", bool(near.all()), ")")
+    assert near.all()
+    assert len(over) < 1e-3 * s.n
+    if len(over):
+        assert float(d[over].max()) < 2 * cutoff_jump(s.table) + TOL_F["ds"] * frms
+    pool.step(10)
+    p1, v1, i1 = pool.get_state(0)
+    obs = pool.observables()[0]
+    assert obs["status"] == 0
+    say("  oracle: 10 velocity-Verlet steps of 1M particles over Verlet lists")
+    pr, vr, ir, _, builds = O.vv_lists(pos, vel, s.box, s.species, s.table, s.dt, 10, s.skin)
+    dr = np.abs((p1 + i1 * s.box) - (pr + (ir + img) * s.box))
+    dv = np.abs(v1 - vr)
+    say("  10 steps: max|dr|", float(dr.max()), "max|dv|", float(dv.max()), "oracle builds", builds,
+        "device builds", obs["n_rebuilds"])
+    assert float(dr.max()) <= 1e-4 and float(dv.max()) <= 1e-4
     pool.close()
 
 

@@ -17,8 +17,8 @@ import pytest
 import md_inputs as I
 from oracle import oracle as O
 from oracle.upload import state_after_upload
-from gpu_helpers import (BAND, TOL_E, TOL_F, force_error, near_cutoff, pool_for,
-                         say)
+from gpu_helpers import (BAND, TOL_E, TOL_F, cutoff_jump, force_error, near_cutoff,
+                         pool_for, say)
 
 pytestmark = pytest.mark.gpu
 PRECS = ["fp32", "ds", "mixed64", "fp64"]
@@ -63,8 +63,7 @@ def test_forces_match_oracle(prec, n, lpp):
     assert err < TOL_F[prec]
     assert abs(e.sum() - er.sum()) <= TOL_E[prec] * abs(er.sum())
     if excl is not None and excl.any():  # one cutoff jump at most
-        jump = abs(O.pair(s.table.rcut[0, 0] * (1 - 1e-12), 1.5, 0.8, 2.0)[1])
-        assert np.abs(f - fr)[excl].max() < 2 * jump + TOL_F[prec] * frms
+        assert np.abs(f - fr)[excl].max() < 2 * cutoff_jump(s.table) + TOL_F[prec] * frms
     pool.close()
 
 
@@ -166,6 +165,38 @@ def test_ten_step_trajectory(prec, lpp):
     tol = 1e-9 if prec == "fp64" else 1e-4
     assert np.abs(d).max() < tol
     assert dv < tol
+    pool.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds"])
+def test_box_that_is_not_a_float(prec):
+    """A box edge with no float32 representation (L = (N/rho)^(1/3) in
+    double): forces at the uploaded state, then 5 steps, a forced re-sort
+    (which folds the particles that crossed a face back into the box by the
+    exact edge), and 5 more steps, against the oracle's 10 steps."""
+    s = I.make_ka(3001, 0.7, jitter=0.06, seed=21, float32_box=False)
+    assert float(np.float32(s.box)) != s.box
+    say("non-float box", prec, repr(s.box))
+    pool = pool_for([s], prec)
+    pos, vel, img = state_after_upload(s.pos, s.vel, s.box, prec)
+    f, e = pool.forces(0)
+    fr, er, _ = O.forces(pos, s.box, s.species, s.table)
+    excl = near_cutoff(pos, s.box, s.species, s.table, lambda a, b: s.table.rcut[a, b])
+    err, frms = force_error(f, fr, excl)
+    say("  e_F", err, "excluded", int(excl.sum()))
+    assert err < TOL_F[prec]
+    pool.step(5)
+    pool.rebuild_neighbours()
+    pool.step(5)
+    p1, v1, i1 = pool.get_state(0)
+    pr, vr, ir, _ = O.vv(pos, vel, s.box, s.species, s.table, s.dt, 10)
+    d = np.abs((p1 + i1 * s.box) - (pr + (ir + img) * s.box)).max()
+    dv = np.abs(v1 - vr).max()
+    crossed = int(np.count_nonzero(i1 != img))
+    say("  10 steps: max|dr|", d, "max|dv|", dv, "face crossings", crossed)
+    assert crossed > 0
+    assert d < 1e-4 and dv < 1e-4
+    assert np.all((p1 >= 0) & (p1 < s.box))
     pool.close()
 
 

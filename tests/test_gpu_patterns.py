@@ -235,3 +235,67 @@ def test_error_paths():
     pool.step(10)
     assert pool.observables()[1]["step"] == 10
     pool.close()
+
+
+def _imploding_ka(n=3001, speed=15.0, seed=41):
+    """A KA replica whose inner sphere (radius 0.45 L) is given an inward
+    radial velocity of up to `speed` on top of its thermal velocities: the
+    local density in the centre rises by ~1.8x within ~60 steps, so its
+    Verlet lists outgrow a capacity that equilibrium replicas never reach
+    (checked on the CPU with the oracle: the largest count within 2.8 sigma
+    goes 124 -> 240 and positions stay finite)."""
+    s = I.make_ka(n, 0.6, jitter=0.05, seed=seed)
+    d = s.pos - s.box / 2
+    r = np.linalg.norm(d, axis=1)
+    m = r < 0.45 * s.box
+    v = s.vel.copy()
+    v[m] -= speed * d[m] / np.maximum(r[m], 1e-9)[:, None] * np.minimum(1.0, r[m] / 2.0)[:, None]
+    s.vel = v
+    return s
+
+
+def test_list_overflow_mid_run_stops_the_replica_and_spares_the_others():
+    """A replica whose Verlet lists outgrow the pool's capacity mid-run stops
+    at the step whose rebuild overflowed (no step runs on a truncated
+    list); md_poll and md_observables report MD_E_CAPACITY with the bit in
+    its status; launching calls refuse until it is detached; the other
+    replicas of the pool are bitwise what they are alone."""
+    from paper_0912_3824_amd import mdx
+    normal = [I.make_ka(1500, 0.6, jitter=0.05, seed=42), I.make_ka(3001, 0.5, jitter=0.05, seed=43)]
+    boom = _imploding_ka()
+    cap = 160
+    pool = pool_for(normal + [boom], "ds", nbr_capacity=cap)
+    pool.step(200)
+    steps, status = pool.poll()
+    say("overflow run: steps", steps[:3].tolist(), "status", status[:3].tolist())
+    assert status[2] & mdx.MD_ST_LIST_OVERFLOW
+    assert 0 < steps[2] < 200
+    assert steps[0] == 200 and steps[1] == 200
+    assert not (status[0] & 0xFF) and not (status[1] & 0xFF)
+    with pytest.raises(mdx.MdError) as ei:
+        pool.observables()
+    assert ei.value.status == mdx.MD_E_CAPACITY
+    obs = pool.observables(check=False)
+    assert obs[2]["status"] & mdx.MD_ST_LIST_OVERFLOW and obs[2]["step"] == steps[2]
+    with pytest.raises(mdx.MdError) as ei:
+        pool.step(10)
+    assert ei.value.status == mdx.MD_E_CAPACITY
+    stopped = _state(pool, 2)
+    pool.detach(2)
+    pool.step(10)
+    mixed = [_state(pool, k) for k in range(2)]
+    assert all(o["status"] == 0 for o in pool.observables()[:2])
+    pool.close()
+    # the stopped state is the state right after the overflowing rebuild:
+    # the same replica alone, advanced exactly that many steps, stops there too
+    alone = pool_for([boom], "ds", nbr_capacity=cap)
+    alone.step(int(steps[2]))
+    st, sb = alone.poll()
+    assert st[0] == steps[2] and sb[0] & mdx.MD_ST_LIST_OVERFLOW
+    assert _same(_state(alone), stopped)
+    alone.close()
+    for k, s in enumerate(normal):
+        ref = pool_for([s], "ds", nbr_capacity=cap)
+        ref.step(210)
+        assert _same(_state(ref), mixed[k]), k
+        ref.close()

@@ -439,3 +439,53 @@ def test_upload_rule_folds_and_rounds_as_defined():
     assert np.array_equal(pds.astype(np.float32), xf.astype(np.float32))  # hi = fl32(x)
     p64, v64, i64 = U.state_after_upload(x, v, L, "fp64")
     assert np.array_equal(p64, xf) and np.array_equal(v64, v) and np.array_equal(i64, img)
+
+
+# ------------------------------------------------------- observables
+def test_pressure_of_an_ideal_gas():
+    """No pair inside the cutoff: W = 0 and E_pot = 0, so the pressure is the
+    ideal-gas value P = N T / V with T = m sum v^2 / (3 N) computed here;
+    catches a wrong volume (L^2, L^3 / 3), a dropped factor 2 on E_kin or a
+    non-zero virial from pairs beyond the cutoff."""
+    L = 40.0
+    g = np.arange(4) * 10.0 + 1.0  # spacing 10 > rc = 2.5, also across the faces
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    n = len(pos)
+    vel = np.random.default_rng(2).normal(size=(n, 3))
+    t = I.lj_table()
+    o = O.observables(pos, vel, L, np.zeros(n, dtype=np.int32), t, mass=1.7)
+    temp = 1.7 * float(np.sum(vel * vel)) / (3 * n)
+    assert o["virial"] == 0.0 and o["epot"] == 0.0
+    assert o["temperature"] == pytest.approx(temp, rel=1e-14)
+    assert o["pressure"] == pytest.approx(n * temp / L ** 3, rel=1e-14)
+
+
+@pytest.mark.parametrize("r,species", [(1.1, (0, 0)), (1.3, (0, 1)), (0.95, (1, 1))])
+def test_pressure_of_two_particles_by_hand(r, species):
+    """Two particles of the KA table at separation r along x: E_pot = V_ts(r),
+    W = r F(r) with F = -dV/dr = (24 eps / r) [2 (sigma/r)^12 - (sigma/r)^6],
+    P = (2 E_kin + W) / (3 L^3), all written out here in exact rationals
+    (fractions), independent of the oracle's pair routine."""
+    from fractions import Fraction as Fr
+    t = I.ka_table()
+    a, b = species
+    eps, sig, rc = (Fr(float(t.eps[a, b])), Fr(float(t.sigma[a, b])), Fr(float(t.rcut[a, b])))
+    L = 12.0
+    pos = np.array([[3.0, 5.0, 5.0], [3.0 + r, 5.0, 5.0]])
+    vel = np.array([[0.3, -0.2, 0.1], [-0.3, 0.2, -0.1]])
+    o = O.observables(pos, vel, L, np.array([a, b], dtype=np.int32), t)
+    rr = Fr(pos[1, 0]) - Fr(pos[0, 0])  # the separation as the doubles hold it
+
+    def v(x):
+        s6 = (sig / x) ** 6
+        return 4 * eps * (s6 * s6 - s6)
+
+    s6 = (sig / rr) ** 6
+    force = 24 * eps / rr * (2 * s6 * s6 - s6)
+    ekin = Fr(1, 2) * sum(Fr(float(c)) ** 2 for c in vel.ravel())
+    epot = v(rr) - v(rc)
+    w = rr * force
+    p = (2 * ekin + w) / (3 * Fr(L) ** 3)
+    assert o["epot"] == pytest.approx(float(epot), rel=1e-13)
+    assert o["virial"] == pytest.approx(float(w), rel=1e-13)
+    assert o["pressure"] == pytest.approx(float(p), rel=1e-13)

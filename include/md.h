@@ -36,9 +36,14 @@
  *   - Errors: no exception crosses the ABI.  Every call returns an md_status;
  *     md_last_error() holds a human-readable description of the last failure
  *     on that handle.  Device-side failures (list overflow, non-finite
- *     coordinates) set sticky per-replica status bits that md_poll() and
- *     md_observables() report and that turn later calls into MD_E_CAPACITY or
- *     MD_E_NONFINITE for that replica.
+ *     coordinates) set sticky per-replica status bits.  A replica with such
+ *     a bit stops on the device at once (the next step launch leaves it
+ *     where it is, so no step runs on a truncated list); the other replicas
+ *     of the pool go on unaffected.  md_poll() and md_observables() report
+ *     the bits and return MD_E_CAPACITY or MD_E_NONFINITE; after that, the
+ *     launching calls (md_step, md_advance) return the same code without
+ *     launching until the replica is detached or restored.  The library
+ *     does not regrow a list: the capacity is fixed by the workspace.
  *   - Threading: one handle must not be used from two host threads at once.
  */
 #ifndef MDX_MD_H
@@ -182,7 +187,11 @@ typedef struct {
 int64_t md_workspace_bytes(const md_config *cfg);
 
 /* Validate a configuration and a replica against it without touching the
- * GPU: returns MD_OK, MD_E_ARG or MD_E_BOX.  `rep` may be NULL. */
+ * GPU: returns MD_OK, MD_E_ARG, MD_E_BOX (the box is shorter than twice the
+ * largest list radius, so the minimum image of Sec. 2.2 would be ambiguous)
+ * or MD_E_CAPACITY (the replica would not fit even an empty pool of this
+ * configuration: more particles than max_particles, or more cells than the
+ * cell arena holds).  `rep` may be NULL. */
 md_status md_validate(const md_config *cfg, const md_replica *rep);
 
 /* Create an empty pool over the caller's workspace (device pointer,
@@ -195,7 +204,12 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes,
 
 /* md_init (the one-call form): md_create, then md_attach of replicas
  * 0..n_rep-1 into slots 0..n_rep-1.  species/pos/vel are host arrays of the
- * concatenated replicas (sum of n entries; pos and vel [n][3] FP64). */
+ * concatenated replicas (sum of n entries; pos and vel [n][3] FP64).  The
+ * problem it sets up is the paper's: N particles of one or two species with
+ * equal masses in a periodic cubic box, pair parameters per species pair,
+ * a cutoff, a time step and a list skin (Sec. 2.2 and Sec. 3; the KA table
+ * of Sec. 5).  On an error after md_create succeeded, *out stays valid so
+ * the caller can read md_last_error and call md_destroy. */
 md_status md_init(const md_config *cfg, const md_replica *reps, int32_t n_rep,
                   const int32_t *species, const double *pos, const double *vel,
                   void *workspace, int64_t ws_bytes, void *hip_stream,
@@ -208,9 +222,9 @@ void md_destroy(md_system *sys);
 
 /* Attach a replica to an empty slot: host FP64 positions (any image; they
  * are wrapped into [0, box)), velocities and species (0/1) are converted to
- * the pool's precision (double-single: hi = fl32(x), lo = fl32(x - hi)),
- * sorted by cell on the host, uploaded, and the replica's first neighbour
- * list is built.  The replica starts at step 0 with full-step velocities.
+ * the pool's precision (double-single: hi = fl32(x), lo = fl32(x - hi),
+ * Sec. 2.4), sorted by cell on the host (the cell binning of Sec. 2.2),
+ * uploaded, and the replica's first Verlet list is built (Sec. 2.2).  The replica starts at step 0 with full-step velocities.
  * Synchronises the stream.  Errors: MD_E_NOSLOT, MD_E_BOX, MD_E_CAPACITY
  * (arena full or list overflow), MD_E_ARG. */
 md_status md_attach(md_system *sys, int32_t slot, const md_replica *rep,
@@ -227,13 +241,18 @@ md_status md_detach(md_system *sys, int32_t slot);
 md_status md_rebuild_neighbours(md_system *sys);
 
 /* Evaluate forces, per-particle energies and virials at the current
- * positions of every attached replica (no state change).  If f_host (n x 3)
+ * positions of every attached replica (no state change): the pair force of
+ * Sec. 3 (12-6 LJ, truncated at the pair's cutoff, energy shifted) over each
+ * particle's Verlet list, the pair term in FP32 and the sum in the pool's
+ * precision (Sec. 2.4), or all in FP64.  If f_host (n x 3)
  * or e_host (n) are non-NULL, synchronises and copies the values of `slot`
  * in particle-id order (input order of md_attach).  Asynchronous when both
  * are NULL (slot is then ignored). */
 md_status md_forces(md_system *sys, int32_t slot, double *f_host, double *e_host);
 
-/* Advance every attached replica by n_steps velocity-Verlet steps (Sec. 2.2):
+/* Advance every attached replica by n_steps velocity-Verlet steps (Sec. 2.2;
+ * refused with MD_E_CAPACITY / MD_E_NONFINITE while a replica reported as
+ * stopped by md_poll or md_observables is attached):
  * per step one fused launch (force, second half-kick, first half-kick of the
  * next step, drift, displacement check) plus the rebuild kernels, which do
  * work only for replicas whose maximum displacement since their last build
@@ -252,12 +271,17 @@ md_status md_advance(md_system *sys, int64_t n_launch);
 
 /* Synchronise and read every slot's completed step count (steps[max_slots],
  * -1 for empty slots) and status bits (status[max_slots]); either may be
- * NULL.  Returns MD_OK even if replicas have error bits set. */
+ * NULL.  The outputs are always written.  Returns MD_OK, or MD_E_CAPACITY /
+ * MD_E_NONFINITE if an attached replica has stopped with an error bit
+ * (md_last_error names the first such slot). */
 md_status md_poll(md_system *sys, int64_t *steps, int32_t *status);
 
-/* Synchronise and compute the observables of every slot (out[max_slots]).
- * Replicas must be at full steps (true after md_step, or once md_advance
- * reached their target). */
+/* Synchronise and compute the observables of every slot (out[max_slots]):
+ * the reductions of Sec. 2.2 (potential energy, kinetic energy and
+ * temperature, momentum, virial and pressure), as FP64 sums in a fixed
+ * order.  Replicas must be at full steps (true after md_step, or once
+ * md_advance reached their target).  `out` is always written; returns
+ * MD_E_CAPACITY / MD_E_NONFINITE like md_poll if a replica has stopped. */
 md_status md_observables(md_system *sys, md_obs *out);
 
 /* Multiply the velocities of a replica by `factor` (velocity rescaling for
@@ -296,9 +320,11 @@ md_status md_sync(md_system *sys);
 /* ---- state access ---------------------------------------------------------- */
 
 /* Copy a replica's state to the host in particle-id order: positions folded
- * into [0, box) (FP64; double-single as hi + lo), velocities, and the image
- * counters such that pos + image * box is the unwrapped trajectory.  Any
- * pointer may be NULL.  Synchronises. */
+ * into [0, box) (FP64; double-single as hi + lo, the value Sec. 2.4 defines),
+ * velocities, and the image counters such that pos + image * box is the
+ * unwrapped trajectory.  pos, vel and image are host arrays of [n][3]
+ * (caller-owned); any pointer may be NULL.  Synchronises.  Errors:
+ * MD_E_NOSLOT, MD_E_HIP, MD_E_STATE (corrupt particle ids). */
 md_status md_get_state(md_system *sys, int32_t slot, double *pos, double *vel,
                        int32_t *image);
 

@@ -73,6 +73,7 @@ struct SlotHost {
     int64_t off = 0, coff = 0, ncell_alloc = 0;
     double L = 0;
     int64_t target = 0;
+    int failed = 0; // error bits (MD_ST_*) seen at the last synchronising call
 };
 
 struct Layout {
@@ -716,7 +717,6 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     r.invL = 1.0 / h.L;
     r.fxs = 4294967296.0 / h.L;
     r.sc = (float)(h.L / 4294967296.0);
-    r.Lf = (float)h.L;
     r.L_hi = (float)h.L;
     r.L_lo = (float)(h.L - (double)r.L_hi);
     r.items3 = h.nd * h.nd * h.nd; // a sort work item covers a cell in every plane
@@ -730,13 +730,15 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
 static void encode_particle(const md_system *s, const RepDev &r, double x[3], double v[3], int *img,
                             uint32_t meta, uint4 *w, uint4 *snap)
 {
+    const double h_L = r.L;
     switch (s->prec) {
     case PREC_FP32: {
         float f[3];
         for (int d = 0; d < 3; ++d) {
+            // x is in [0, L); its float may round up to L or past it, which
+            // is folded by the exact edge (the box need not be a float)
             f[d] = (float)x[d];
-            if (f[d] >= r.Lf) { f[d] -= r.Lf; img[d] += 1; }
-            if (f[d] < 0.0f) { f[d] += r.Lf; img[d] -= 1; }
+            if ((double)f[d] >= h_L) { f[d] = (float)((double)f[d] - h_L); img[d] += 1; }
             x[d] = (double)f[d];
         }
         put_f4(w[0], f[0], f[1], f[2], 0.0f);
@@ -852,6 +854,49 @@ static void release_slot_ranges(md_system *s, SlotHost &h)
     h.attached = false;
 }
 
+// Error bits that stop a replica, and the status a call reports for them.
+constexpr int MD_ST_ERRORS = MD_ST_LIST_OVERFLOW | MD_ST_NONFINITE | MD_ST_LOST | MD_ST_NO_PAD;
+
+static md_status status_of_bits(int bits)
+{
+    if (bits & (MD_ST_NONFINITE | MD_ST_LOST)) return MD_E_NONFINITE;
+    if (bits & (MD_ST_LIST_OVERFLOW | MD_ST_NO_PAD)) return MD_E_CAPACITY;
+    return MD_OK;
+}
+
+// Record the device status bits read at a synchronising call; report the
+// first failed slot.
+static md_status note_failures(md_system *s, const int *bits)
+{
+    md_status worst = MD_OK;
+    for (size_t k = 0; k < s->slots.size(); ++k) {
+        SlotHost &h = s->slots[k];
+        if (!h.attached) continue;
+        h.failed = bits[k] & MD_ST_ERRORS;
+        const md_status st = status_of_bits(h.failed);
+        if (st != MD_OK && worst == MD_OK) {
+            worst = fail(s, st, "replica in slot %d stopped: status bits 0x%x (%s)", (int)k, h.failed,
+                         st == MD_E_CAPACITY ? "a Verlet list exceeded its capacity or could not be padded"
+                                             : "non-finite coordinates");
+        }
+    }
+    return worst;
+}
+
+// Launching calls refuse to run while a replica known to have failed is
+// attached (it would only idle): the caller detaches or restores it first.
+static md_status refuse_if_failed(md_system *s)
+{
+    for (size_t k = 0; k < s->slots.size(); ++k) {
+        const SlotHost &h = s->slots[k];
+        if (h.attached && h.failed)
+            return fail(s, status_of_bits(h.failed),
+                        "replica in slot %d stopped with status bits 0x%x; detach or restore it first", (int)k,
+                        h.failed);
+    }
+    return MD_OK;
+}
+
 static md_status check_slot(md_system *s, int slot, bool want_attached)
 {
     if (!s) return MD_E_ARG;
@@ -912,7 +957,13 @@ md_status md_validate(const md_config *cfg, const md_replica *rep)
     if (st != MD_OK) return st;
     if (rep) {
         if (rep->n < 1 || !(rep->box > 0) || !std::isfinite(rep->box)) return MD_E_ARG;
-        if (rep->box < 2.0 * rlist_max_of(cfg)) return MD_E_BOX;
+        const double rl = rlist_max_of(cfg);
+        if (rep->box < 2.0 * rl) return MD_E_BOX;
+        // would it fit an empty pool: particles in the arena, cells of every
+        // species plane in the cell arena
+        const Layout L = layout_of(cfg);
+        const int64_t nd = cells_per_edge(rep->box, rl);
+        if (rep->n > cfg->max_particles || cfg->n_species * nd * nd * nd + 1 > L.cells) return MD_E_CAPACITY;
     }
     return MD_OK;
 }
@@ -1101,6 +1152,7 @@ md_status md_detach(md_system *s, int32_t slot)
     }
     HIPCHK(s, hipStreamSynchronize(s->stream));
     release_slot_ranges(s, h);
+    h.failed = 0;
     return upload_items(s);
 }
 
@@ -1152,6 +1204,7 @@ md_status md_step(md_system *s, int64_t n_steps)
     if (!s) return MD_E_ARG;
     if (n_steps < 0 || n_steps > (1LL << 30)) return fail(s, MD_E_ARG, "n_steps out of range");
     if (n_steps == 0) return MD_OK;
+    if (md_status st = refuse_if_failed(s); st != MD_OK) return st;
     for (auto &h : s->slots)
         if (h.attached) {
             if (h.target + n_steps > 2000000000LL) return fail(s, MD_E_ARG, "step counter would overflow");
@@ -1175,6 +1228,7 @@ md_status md_advance(md_system *s, int64_t n_launch)
 {
     if (!s) return MD_E_ARG;
     if (n_launch < 0) return fail(s, MD_E_ARG, "n_launch < 0");
+    if (md_status st = refuse_if_failed(s); st != MD_OK) return st;
     return run_launches(s, n_launch);
 }
 
@@ -1192,7 +1246,7 @@ md_status md_poll(md_system *s, int64_t *steps, int32_t *status)
         if (steps) steps[k] = att ? c[k].x : -1;
         if (status) status[k] = att ? (stv[k] | (c[k].y ? MD_ST_AT_FULL_STEP : 0)) : 0;
     }
-    return MD_OK;
+    return note_failures(s, stv.data());
 }
 
 md_status md_observables(md_system *s, md_obs *out)
@@ -1238,7 +1292,7 @@ md_status md_observables(md_system *s, md_obs *out)
         o.n_rebuilds = nr[k];
         o.status = stv[k];
     }
-    return MD_OK;
+    return note_failures(s, stv.data());
 }
 
 md_status md_scale_velocities(md_system *s, int32_t slot, double factor)

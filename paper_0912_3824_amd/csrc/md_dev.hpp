@@ -46,7 +46,6 @@ struct RepDev {
     double invL;  // 1 / L
     double fxs;   // 2^32 / L   (double -> fixed point)
     float sc;     // L / 2^32   (fixed point unit in length units)
-    float Lf;     // L rounded to float (FP32 wrap)
     float L_hi, L_lo; // L as double-single
     int items3, items4; // work items of the sort and list-build kernels
     int bparts;   // list-build work items per row segment (its members split evenly)
@@ -106,6 +105,11 @@ __host__ __device__ __forceinline__ double bits_of_meta(uint32_t m)
     return w;
 #endif
 }
+
+// Per-replica status bits written by the kernels (the MD_ST_* values of the
+// C ABI): list overflow, non-finite position, lost particles, unpaddable
+// list.  Any of them stops the replica.
+#define ST_HALT (1 | 2 | 4 | 8)
 
 #define SLOT_SHIFT 4
 #define MAX_ARENA_SLOTS (1 << 28) // list entries are 32-bit byte offsets (slot x 16)

@@ -156,9 +156,9 @@ __device__ __forceinline__ void move_store(const PermArgs &a, const RepDev &rp, 
         float4 p = u4_as_f4(mv.st[0]);
         float *c[3] = {&p.x, &p.y, &p.z};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if (*c[d] < 0.0f) { *c[d] += rp.Lf; *im[d] -= 1; }
-            if (*c[d] >= rp.Lf) { *c[d] -= rp.Lf; *im[d] += 1; }
+        for (int d = 0; d < 3; ++d) { // fold by the exact edge (the box need not be a float)
+            if (*c[d] < 0.0f) { *c[d] = (float)((double)*c[d] + rp.L); *im[d] -= 1; }
+            if ((double)*c[d] >= rp.L) { *c[d] = (float)((double)*c[d] - rp.L); *im[d] += 1; }
         }
         a.sc_st[0][dst] = f4_as_u4(p);
         a.sc_st[1][dst] = mv.st[1];

@@ -378,11 +378,15 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         mode = M_FIN;
     } else {
         const int tgt = a.target[r];
-        mode = ctl.x < tgt ? M_ADV : (ctl.y ? M_IDLE : M_FIN);
+        // A replica with an error bit (a list that overflowed its capacity
+        // or could not be padded, lost particles, a non-finite position)
+        // stops where it is: no step runs on a truncated list.
+        const bool halted = (a.status[r] & ST_HALT) != 0;
+        mode = halted ? M_IDLE : (ctl.x < tgt ? M_ADV : (ctl.y ? M_IDLE : M_FIN));
         if (i == rp.off && sub == 0) { // the replica's first particle owns its control words
             Ctl nx = ctl;
             if (mode == M_ADV) { nx.x = ctl.x + 1; nx.y = 0; }
-            else nx.y = 1;
+            else if (!halted) nx.y = 1;
             a.ctl_next[r] = nx;
             a.need_other[r] = 0;
         }

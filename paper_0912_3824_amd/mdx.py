@@ -21,6 +21,9 @@ MD_FP32, MD_DS, MD_MIXED64, MD_FP64 = 0, 1, 2, 3
 PRECISIONS = {"fp32": MD_FP32, "ds": MD_DS, "mixed64": MD_MIXED64, "fp64": MD_FP64}
 MD_ST_LIST_OVERFLOW, MD_ST_NONFINITE, MD_ST_LOST, MD_ST_AT_FULL_STEP = 1, 2, 4, 256
 
+MD_E_CAPACITY, MD_E_NONFINITE = -4, -5
+MD_ST_NO_PAD = 8
+
 STATUS_NAMES = {0: "MD_OK", -1: "MD_E_ARG", -2: "MD_E_BOX", -3: "MD_E_WORKSPACE",
                 -4: "MD_E_CAPACITY", -5: "MD_E_NONFINITE", -6: "MD_E_HIP",
                 -7: "MD_E_NOSLOT", -8: "MD_E_STATE"}
@@ -354,6 +357,12 @@ class MdSystem:
         self.sizes[slot] = int(n)
         self.boxes[slot] = float(box)
 
+    def validate(self, n: int, box: float) -> int:
+        """md_validate for a replica of n particles in a box of edge `box`
+        against this pool's configuration: 0, or the status it would get in
+        an empty pool (MD_E_BOX, MD_E_CAPACITY, MD_E_ARG).  Host only."""
+        return md_validate(self.cfg, n, box)
+
     def attach_system(self, slot: int, s):
         """Attach an md_inputs.System."""
         self.attach(slot, s.n, s.box, s.species, s.pos, s.vel)
@@ -388,15 +397,24 @@ class MdSystem:
         self._check(self.lib.md_advance(self.h, int(n_launch)), "md_advance")
 
     def poll(self):
+        """(steps, status) of every slot (md_poll).  A replica that stopped
+        with an error bit is reported in `status`, not raised: md_poll's
+        MD_E_CAPACITY / MD_E_NONFINITE are how the C ABI flags it."""
         steps = np.zeros(self.max_slots, dtype=np.int64)
         status = np.zeros(self.max_slots, dtype=np.int32)
-        self._check(self.lib.md_poll(self.h, steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                     _ip(status)), "md_poll")
+        st = self.lib.md_poll(self.h, steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ip(status))
+        if st not in (0, MD_E_CAPACITY, MD_E_NONFINITE):
+            self._check(st, "md_poll")
         return steps, status
 
-    def observables(self):
+    def observables(self, check: bool = True):
+        """Observables of every slot (md_observables).  With check=False a
+        replica stopped by an error bit is reported in its 'status' instead
+        of raising."""
         out = (MdObs * self.max_slots)()
-        self._check(self.lib.md_observables(self.h, out), "md_observables")
+        st = self.lib.md_observables(self.h, out)
+        if check or st not in (MD_E_CAPACITY, MD_E_NONFINITE):
+            self._check(st, "md_observables")
         return [o.as_dict() for o in out]
 
     def scale_velocities(self, slot: int, factor: float):

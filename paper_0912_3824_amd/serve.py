@@ -10,7 +10,13 @@ graph-captured steps.  Between chunks it
     final state out and releasing their slot and arena ranges (md_detach);
   * admits queued jobs in arrival order while a slot is free and the job's
     HBM footprint (its particle and cell ranges in the pool's arena) fits
-    (md_attach refuses with MD_E_CAPACITY otherwise; the job then waits).
+    (md_attach refuses with MD_E_CAPACITY otherwise; the job then waits);
+  * rejects, with an error result, a job that could never run: one that
+    would not fit even an empty pool (md_validate), or one whose attach
+    still fails once nothing else is running (e.g. its first Verlet lists
+    exceed the pool's capacity);
+  * retires with an error result a job whose replica stopped with an error
+    bit (a list that outgrew its capacity, non-finite coordinates).
 
 A replica's trajectory does not depend on the other replicas in the pool,
 so every job's result is bitwise the one it would get alone.
@@ -35,9 +41,10 @@ class JobResult:
     arrival: float
     admitted: float
     finished: float
-    pos: np.ndarray
-    vel: np.ndarray
-    image: np.ndarray
+    pos: Optional[np.ndarray]
+    vel: Optional[np.ndarray]
+    image: Optional[np.ndarray]
+    error: Optional[str] = None
 
     @property
     def latency(self) -> float:
@@ -56,9 +63,11 @@ class Server:
 
     def __init__(self, table, precision="ds", dt=0.001, skin=0.3, max_slots=32,
                  max_particles=2_000_000, chunk_steps=256, device="cuda:0",
-                 make_system: Optional[Callable] = None):
-        cfg = mdx.make_config(table, precision, dt, skin, max_slots, max_particles)
-        self.pool = mdx.MdSystem(cfg, device=device)
+                 make_system: Optional[Callable] = None, pool=None):
+        if pool is None:
+            cfg = mdx.make_config(table, precision, dt, skin, max_slots, max_particles)
+            pool = mdx.MdSystem(cfg, device=device)
+        self.pool = pool
         self.chunk = int(chunk_steps)
         self.max_slots = max_slots
         self.make_system = make_system
@@ -73,20 +82,27 @@ class Server:
         per = mdx.md_workspace_bytes(probe) / (1 << 20)
         return int(hbm_budget / per)
 
-    def _try_admit(self, job, system, now) -> bool:
+    def _try_admit(self, job, system, now) -> str:
+        """'admitted', 'wait' (no slot or arena space now) or an error text
+        (the job can never run in this pool)."""
         if not self.free:
-            return False
+            return "wait"
+        st = self.pool.validate(system.n, system.box)
+        if st != 0:
+            return f"{mdx.STATUS_NAMES.get(st, st)}: does not fit an empty pool"
         slot = self.free[0]
         try:
             self.pool.attach(slot, system.n, system.box, system.species, system.pos, system.vel)
         except mdx.MdError as e:
-            if e.status == -4:  # arena full: wait for a job to finish
-                return False
-            raise
+            if e.status != mdx.MD_E_CAPACITY:
+                raise
+            if self.running:  # arena full: wait for a job to finish
+                return "wait"
+            return str(e)  # refused by an empty pool: it never fits
         self.free.pop(0)
         self.pool.set_target(slot, job.steps)
         self.running[slot] = {"job": job, "admitted": now}
-        return True
+        return "admitted"
 
     def run(self, jobs: List, time_scale: float = 1.0, log: Optional[Callable] = None) -> dict:
         """Serve `jobs` (md_inputs.Job, sorted by arrival).  Arrival times are
@@ -101,16 +117,22 @@ class Server:
         while pi < len(pending) or queue or self.running:
             now = time.perf_counter() - t0
             while pi < len(pending) and pending[pi].arrival * time_scale <= now:
-                queue.append(pending[pi])
+                queue.append((pending[pi], self.make_system(pending[pi])))  # built once per job
                 pi += 1
             # admission in arrival order (head-of-line: a job that does not fit
-            # blocks later ones, so large jobs are not starved)
+            # yet blocks later ones, so large jobs are not starved)
             while queue:
-                job = queue[0]
-                sys_ = self.make_system(job)
-                if not self._try_admit(job, sys_, time.perf_counter() - t0):
+                job, sys_ = queue[0]
+                now = time.perf_counter() - t0
+                verdict = self._try_admit(job, sys_, now)
+                if verdict == "wait":
                     break
                 queue.pop(0)
+                if verdict != "admitted":
+                    results.append(JobResult(job.job_id, sys_.n, job.steps, job.arrival * time_scale,
+                                             now, now, None, None, None, error=verdict))
+                    if log:
+                        log(f"job {job.job_id} n={sys_.n} rejected: {verdict}")
             if not self.running:
                 if pi < len(pending):  # idle until the next arrival
                     time.sleep(max(0.0, pending[pi].arrival * time_scale - (time.perf_counter() - t0)))
@@ -123,8 +145,18 @@ class Server:
             for slot in list(self.running):
                 r = self.running[slot]
                 job = r["job"]
-                if status[slot] & 0xFF:
-                    raise mdx.MdError(-4, f"job {job.job_id} failed with status {status[slot]}")
+                if status[slot] & 0xFF:  # the replica stopped with an error bit
+                    results.append(JobResult(job.job_id, self.pool.sizes[slot], job.steps,
+                                             job.arrival * time_scale, r["admitted"], now, None, None,
+                                             None, error=f"stopped at step {int(steps[slot])} with "
+                                                         f"status bits {int(status[slot]) & 0xFF:#x}"))
+                    self.pool.detach(slot)
+                    self.free.append(slot)
+                    self.free.sort()
+                    del self.running[slot]
+                    if log:
+                        log(f"job {job.job_id} failed: {results[-1].error}")
+                    continue
                 if steps[slot] >= job.steps and status[slot] & mdx.MD_ST_AT_FULL_STEP:
                     pos, vel, img = self.pool.get_state(slot)
                     results.append(JobResult(job.job_id, self.pool.sizes[slot], job.steps,
@@ -139,9 +171,10 @@ class Server:
                         log(f"job {job.job_id} n={results[-1].n} steps={job.steps} "
                             f"latency {results[-1].latency:.3f}s")
         wall = time.perf_counter() - t0
-        lat = np.array([r.latency for r in results])
+        lat = np.array([r.latency for r in results if r.error is None])
         return {
             "results": sorted(results, key=lambda r: r.job_id),
+            "failed": sorted(r.job_id for r in results if r.error is not None),
             "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "particle_steps": int(work),

@@ -21,24 +21,32 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X vendor peaks
+# MI355X vendor peaks.  VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s for FP32 (and FP64) without packed-FP32 dual
+# issue, which this build does not use; the 157.3 TFLOP/s headline needs it.
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 VALU
-# instruction occupies a SIMD for 4 cycles); packed-FP32 dual issue is not used.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12          # 78.6
+VALU_PACKED_PEAK_TFLOPS = 2 * VALU_PEAK_TFLOPS              # 157.3
+# VALU issue rate: a wave64 instruction occupies a SIMD16 for 4 cycles
+VALU_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.3 T lane-ops/s
 
-# Algorithmic work of one fused step per particle with L list entries.
-# Bytes: list count 4 + list 4L + own snapshot + state read/write + new
-# snapshot + reference position + cell-count atomic (neighbour snapshots are
-# re-reads of data counted once).  VALU lane-ops: per list entry (separation,
-# r^2, species select, pair term with a quarter-rate reciprocal counted as 4,
-# cutoff mask, accumulation) and per particle (two kicks, drift, snapshot,
-# displacement test).
+# Algorithmic work of one fused step per particle-step, with L list entries
+# and L_in of them inside the cutoff:
+#   bytes: list count 4 + list 4L + own snapshot + state read and write +
+#          new snapshot + reference position + cell-count atomic (neighbour
+#          snapshots are re-reads of records counted once);
+#   flops (the method's, not the kernel's instructions): 17 per list entry
+#          (separation, minimum image, r^2, cutoff test) and 21 per pair
+#          inside the cutoff (pair term, energy, virial, accumulation); the
+#          double-single modes add 27 per pair (DS accumulation) and 3 per
+#          entry (the low-word difference).
+# `ops_entry` / `ops_particle` are the kernel's own VALU lane-ops (its
+# compiled instruction mix), kept apart as issue utilisation.
 ALGO = {
-    "fp32": {"bytes": (4, 120), "ops_entry": 31, "ops_particle": 45},
-    "ds": {"bytes": (4, 152), "ops_entry": 52, "ops_particle": 180},
-    "mixed64": {"bytes": (4, 152), "ops_entry": 35, "ops_particle": 50},
-    "fp64": {"bytes": (4, 200), "ops_entry": 48, "ops_particle": 50},
+    "fp32": {"bytes": (4, 120), "flop_entry": 17, "flop_pair": 21, "ops_entry": 31, "ops_particle": 45},
+    "ds": {"bytes": (4, 152), "flop_entry": 20, "flop_pair": 48, "ops_entry": 52, "ops_particle": 180},
+    "mixed64": {"bytes": (4, 152), "flop_entry": 17, "flop_pair": 21, "ops_entry": 35, "ops_particle": 50},
+    "fp64": {"bytes": (4, 200), "flop_entry": 17, "flop_pair": 21, "ops_entry": 48, "ops_particle": 50},
 }
 
 WORKLOADS = {
@@ -96,33 +104,88 @@ def equilibrate(pool, systems, steps: int, every: int = 100):
                 pool.scale_velocities(slot, math.sqrt(s.temperature / t))
 
 
-def cpu_baseline(system, budget_s: float = 15.0):
-    """The FP64 oracle (brute force) timed on a bounded sample of the same
-    workload: forces on m randomly chosen particles of the system, m grown
-    until one timed call takes about budget_s (bounded to ~2 budgets of CPU
-    time in total)."""
+def pairs_inside_cutoff(pos, box, species, table, sample=20000, seed=3):
+    """Mean number of partners inside the pair's cutoff per particle, from a
+    periodic kd-tree search around a random sample of particles (scipy): the
+    L_in of the algorithmic flop count."""
     import numpy as np
-    from oracle import oracle as O
-    O.build(force=False)
-    rng = np.random.default_rng(1)
+    from scipy.spatial import cKDTree
+    p = np.mod(pos, box)
+    p[p >= box] = 0.0
+    tree = cKDTree(p, boxsize=box)
+    rng = np.random.default_rng(seed)
+    sel = rng.choice(len(p), size=min(sample, len(p)), replace=False)
+    sp = species if table.n_species > 1 else np.zeros(len(p), dtype=int)
+    rmax = table.max_rcut()
+    tot = 0
+    for i, js in zip(sel, tree.query_ball_point(p[sel], rmax)):
+        js = np.asarray([j for j in js if j != i], dtype=np.int64)
+        if len(js) == 0:
+            continue
+        d = p[js] - p[i]
+        d -= box * np.rint(d / box)
+        r2 = (d * d).sum(axis=1)
+        rc = table.rcut[sp[i], sp[js]]
+        tot += int(np.count_nonzero(r2 < rc * rc))
+    return tot / len(sel)
+
+
+_CPU_CHILD = r"""
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+import md_inputs as I
+from oracle import oracle as O
+O.build(force=False)
+n, T, m = int(sys.argv[2]), float(sys.argv[3]), int(sys.argv[4])
+s = I.make_ka(n, T, seed=20240101)
+t0 = time.perf_counter(); b1 = O.vv_lists(s.pos, s.vel, s.box, s.species, s.table, s.dt, 1, s.skin)[4]
+t1 = time.perf_counter(); b2 = O.vv_lists(s.pos, s.vel, s.box, s.species, s.table, s.dt, 1 + m, s.skin)[4]
+t2 = time.perf_counter()
+print(json.dumps({"n": n, "m": m, "t_one": t1 - t0, "t_more": t2 - t1, "extra_builds": b2 - b1}))
+"""
+
+
+def _cpu_run(n, temperature, m, threads):
+    """The oracle's Verlet-list velocity Verlet (FP64) on the KA system of n
+    particles, in a child process with `threads` OpenMP threads: one step,
+    then 1 + m steps from the same start; the difference is m steps between
+    list builds."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, "-c", _CPU_CHILD, ROOT, str(n), str(temperature), str(m)],
+                         env=env, capture_output=True, text=True, check=True)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    per_step = (r["t_more"] - r["t_one"]) / m
+    return {"value": n / per_step, "per_step_s": per_step, "t_one_step_with_build_s": r["t_one"],
+            "wall_s": r["t_one"] + r["t_more"], "extra_builds": r["extra_builds"]}
+
+
+def cpu_baseline(n: int, temperature: float):
+    """The FP64 oracle's cell-list / Verlet-list route (the paper's CPU code
+    also used neighbour lists) timed on the host cores, on a bounded sample
+    of the workload: on all cores, 1 + m steps of the full system against
+    one step (m chosen for ~10 s); on one thread, the same on a smaller
+    system of the same kind (a cell-list code's cost per particle does not
+    depend on N).  The rate covers the m steps and any list rebuild among
+    them (stated); the time of the first build is stated beside it."""
     cores = len(os.sched_getaffinity(0))
-    n = system.n
-    m = min(n, 256 if n > 100000 else 2048)
-    spent = 0.0
-    while True:
-        sel = rng.choice(n, size=m, replace=False).astype(np.int32)
-        t0 = time.perf_counter()
-        O.forces(system.pos, system.box, system.species, system.table, sel)
-        dt = time.perf_counter() - t0
-        spent += dt
-        if m >= n or dt >= 0.6 * budget_s or spent + 2 * dt > 2 * budget_s:
-            break
-        m = int(min(n, m * min(8.0, max(1.5, budget_s / max(dt, 1e-3)))))
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": m / dt, "unit": "particle-steps/s", "cores": min(threads, cores),
-            "kind": "oracle",
-            "sample": f"brute-force FP64 forces (one step's force work) on {m} randomly chosen "
-                      f"particles of the N={n} system, {dt:.1f} s"}
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    probe = _cpu_run(n, temperature, 1, threads)
+    m = int(max(2, min(40, 10.0 / max(probe["per_step_s"], 1e-3))))
+    full = _cpu_run(n, temperature, m, threads)
+    n1 = min(n, 131072)
+    probe1 = _cpu_run(n1, temperature, 1, 1)
+    m1 = int(max(2, min(20, 8.0 / max(probe1["per_step_s"], 1e-3))))
+    one = _cpu_run(n1, temperature, m1, 1)
+    return {"value": full["value"], "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 velocity Verlet over cell-built Verlet lists (oracle cell-list route), "
+                      f"{m} steps of the full N={n} system ({full['extra_builds']} list rebuilds among "
+                      f"them), {threads} threads "
+                      f"({full['per_step_s']:.3f} s per step; one step with its list build "
+                      f"{full['t_one_step_with_build_s']:.2f} s)",
+            "single_thread": {"value": one["value"], "unit": "particle-steps/s", "cores": 1,
+                              "sample": f"the same on N={n1} (same density and temperature), {m1} steps "
+                                        f"({one['extra_builds']} rebuilds), {one['per_step_s']:.3f} s per step"}}
 
 
 def main():
@@ -206,31 +269,40 @@ def main():
 
     a = ALGO[prec]
     k_ms = prof["step_kernel_ms"]
+    p_end, _, _ = pool.get_state(0)
+    s0 = systems[0] if len(systems) == 1 else max(systems, key=lambda q: q.n)
+    l_in = pairs_inside_cutoff(p_end if len(systems) == 1 else s0.pos, s0.box, s0.species, s0.table)
     bytes_launch = n_total * (a["bytes"][0] * mean_list + a["bytes"][1])
+    flops_launch = n_total * (a["flop_entry"] * mean_list + a["flop_pair"] * l_in)
     ops_launch = n_total * (a["ops_entry"] * mean_list + a["ops_particle"])
     hbm_gbs = bytes_launch / (k_ms * 1e-3) / 1e9
-    alu_tops = ops_launch / (k_ms * 1e-3) / 1e12
-    t_hbm = bytes_launch / (HBM_PEAK_GBS * 1e9)
-    t_alu = ops_launch / (VALU_PEAK_TOPS * 1e12)
-    if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": round(alu_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s (VALU lane-ops)", "frac": round(alu_tops / VALU_PEAK_TOPS, 4)}
+    tflops = flops_launch / (k_ms * 1e-3) / 1e12
+    hbm_frac = hbm_gbs / HBM_PEAK_GBS
+    alu_frac = tflops / VALU_PEAK_TFLOPS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(VALU_PEAK_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+                "unit": "GB/s", "frac": round(hbm_frac, 4)}
+    roof["traffic"] = read_traffic(args.workload, prec, n_total, args.cell_order)
     roof["kernel"] = f"k_step<{prec}> (fused force + velocity Verlet)"
     roof["kernel_ms"] = round(k_ms, 5)
     roof["algorithmic_bytes_per_launch"] = int(bytes_launch)
-    roof["algorithmic_ops_per_launch"] = int(ops_launch)
-    roof["hbm_frac"] = round(hbm_gbs / HBM_PEAK_GBS, 4)
-    roof["alu_frac"] = round(alu_tops / VALU_PEAK_TOPS, 4)
-    traffic = read_traffic(args.workload, prec, n_total, args.cell_order)
-    roof["traffic"] = traffic
+    roof["algorithmic_flops_per_launch"] = int(flops_launch)
+    roof["list_entries_per_particle"] = round(mean_list, 3)
+    roof["pairs_inside_cutoff_per_particle"] = round(l_in, 3)
+    roof["hbm_frac"] = round(hbm_frac, 4)
+    roof["alu_frac"] = round(alu_frac, 4)
+    roof["alu_frac_of_packed_peak"] = round(tflops / VALU_PACKED_PEAK_TFLOPS, 4)
+    # the kernel's own VALU lane-ops against the issue rate (not a roofline)
+    roof["valu_issue_utilisation"] = round(ops_launch / (k_ms * 1e-3) / 1e12 / VALU_ISSUE_PEAK_TOPS, 4)
     log(f"roofline: {roof}")
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(systems[0] if len(systems) == 1 else max(systems, key=lambda s: s.n))
+        big = systems[0] if len(systems) == 1 else max(systems, key=lambda q: q.n)
+        cpu = cpu_baseline(big.n, big.temperature)
         log(f"cpu baseline: {cpu}")
 
     out = {

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 3
+#define MD_ABI_VERSION 4
 
 typedef struct md_system md_system;
 
@@ -301,6 +301,20 @@ md_status md_scale_velocities(md_system *sys, int32_t slot, double factor);
  * Asynchronous.  Errors: MD_E_NOSLOT, MD_E_ARG, MD_E_HIP. */
 md_status md_thermostat(md_system *sys, int32_t slot, double temperature, uint64_t seed, int64_t call,
                         int32_t remove_mean);
+
+/* md_thermostat for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, same arithmetic and bitwise the same velocities as
+ * md_thermostat, but it neither allocates nor touches the pool's scratch
+ * rows (which md_forces results occupy): its per-call partial sums live in
+ * a static device array inside the library, one per GPU, of at most 16384
+ * chunks of 4096 particles, so a replica may hold at most 67,108,864
+ * particles (else MD_E_CAPACITY, nothing launched).  The array is shared by
+ * every call on a GPU: calls that overlap on one GPU (two streams, two host
+ * threads) race and must not be issued.  Asynchronous.  Errors as
+ * md_thermostat, plus MD_E_CAPACITY and MD_E_STATE. */
+md_status md_thermostat_noalloc(md_system *sys, int32_t slot, double temperature, uint64_t seed,
+                                int64_t call, int32_t remove_mean);
 
 /* Benchmark helper: advance every attached replica by n_steps like md_step
  * but with eager launches, timing each step's fused kernel and its group of

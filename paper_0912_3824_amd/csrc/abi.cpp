@@ -112,6 +112,7 @@ struct md_system {
     int parity = 0; // parity of the snapshot the next step reads
     int lpp = 1;    // lanes per particle of the force sum
     int n_cu = 0;   // compute units of the device
+    int dev = 0;    // the device current at md_create
     int grid_perm = 0, grid_build = 0; // one full residency of the rebuild kernels
     std::map<int, hipGraphExec_t> graphs;
     std::string err;
@@ -1007,10 +1008,11 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            size_grids(s) != MD_OK) {
+            size_grids(s) != MD_OK || thermo_scratch_init(dev) != hipSuccess) {
             delete s;
             return MD_E_HIP;
         }
+        s->dev = dev;
     }
     s->slots.assign(L.slots, SlotHost());
     s->parena.reset(L.P);
@@ -1336,6 +1338,43 @@ md_status md_thermostat(md_system *s, int32_t slot, double temperature, uint64_t
     a.nchunk = (h.n + 4095) / 4096;
     a.remove_mean = remove_mean ? 1 : 0;
     a.x0 = ((seed & 0xFFFFFFFFULL) << 16) | 0x330EULL; // the state srand48(seed) sets
+    a.call = call;
+    a.temperature = temperature;
+    a.mass = s->cfg.mass;
+    a.scale = std::sqrt(temperature / s->cfg.mass);
+    HIPCHK(s, launch_thermostat(s->prec, a, s->stream));
+    return MD_OK;
+}
+
+md_status md_thermostat_noalloc(md_system *s, int32_t slot, double temperature, uint64_t seed, int64_t call,
+                                int32_t remove_mean)
+{
+    // The same kernels and arithmetic as md_thermostat; the chunk partial
+    // sums go to the library's file-scope scratch array of this device, the
+    // drawn velocities are drawn again when applied, and nothing here
+    // allocates (host or device).
+    md_status st = check_slot(s, slot, true);
+    if (st != MD_OK) return st;
+    if (!(temperature > 0) || !std::isfinite(temperature)) return fail(s, MD_E_ARG, "temperature must be positive");
+    if (call < 0 || call > ((int64_t)1 << 40)) return fail(s, MD_E_ARG, "call index out of range");
+    const SlotHost &h = s->slots[slot];
+    const int nchunk = (h.n + 4095) / 4096;
+    if (nchunk > THERMO_SCRATCH_CHUNKS)
+        return fail(s, MD_E_CAPACITY, "md_thermostat_noalloc: %d particles exceed its scratch limit of %d",
+                    h.n, THERMO_SCRATCH_CHUNKS * 4096);
+    double *scr = thermo_scratch(s->dev);
+    if (!scr) return fail(s, MD_E_STATE, "scratch array of device %d not set up", s->dev);
+    ThermoArgs a;
+    memset(&a, 0, sizeof a);
+    a.A = arena_of(s);
+    a.obs = nullptr;
+    a.partial = scr;
+    a.off = (int)h.off;
+    a.n = h.n;
+    a.chunk0 = 0;
+    a.nchunk = nchunk;
+    a.remove_mean = remove_mean ? 1 : 0;
+    a.x0 = ((seed & 0xFFFFFFFFULL) << 16) | 0x330EULL;
     a.call = call;
     a.temperature = temperature;
     a.mass = s->cfg.mass;

@@ -1,5 +1,7 @@
 // Observables, velocity scaling, the double-single self-test and stream-
 // ordered control writes, with their launchers.
+#include <mutex>
+
 #include "dev_common.hpp"
 
 // ------------------------------------------------------------ k_obs_reduce
@@ -104,8 +106,26 @@ __device__ __forceinline__ unsigned long long r48_element(unsigned long long x0,
 
 #define TH_CHUNK 4096
 
-// Draw Maxwell-Boltzmann velocities (Box-Muller) into the scratch rows and
-// reduce sum(v) and sum(v^2) per chunk of TH_CHUNK particles.
+// The Maxwell-Boltzmann velocity of particle id at this call (Box-Muller on
+// four leap-frogged rand48 elements); a pure function of (seed, call, id).
+__device__ __noinline__ void thermo_velocity(const ThermoArgs &a, int id, double v[3])
+{
+    const unsigned long long base = (unsigned long long)id + (unsigned long long)a.n * (4ULL * a.call);
+    double u[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        u[r] = (double)r48_element(a.x0, base + (unsigned long long)a.n * r) * (1.0 / 281474976710656.0);
+    const double ra = sqrt(-2.0 * log(1.0 - u[0])), rb = sqrt(-2.0 * log(1.0 - u[2]));
+    const double ph = 6.283185307179586 * u[1], ph2 = 6.283185307179586 * u[3];
+    v[0] = a.scale * ra * cos(ph);
+    v[1] = a.scale * ra * sin(ph);
+    v[2] = a.scale * rb * cos(ph2);
+}
+
+// Draw Maxwell-Boltzmann velocities into the scratch rows (when a.obs is
+// set; the allocation-free form draws them again when it applies them) and
+// reduce sum(v) and sum(v^2) per chunk of TH_CHUNK particles into
+// a.partial[(chunk0 + c) * 8 + q].
 __global__ void __launch_bounds__(256) k_thermo_draw(const ThermoArgs a)
 {
     __shared__ double red[4][256];
@@ -116,16 +136,12 @@ __global__ void __launch_bounds__(256) k_thermo_draw(const ThermoArgs a)
         const int i = a.off + k;
         const int id = a.A.meta[i].w;
         if (id < 0 || id >= a.n) continue;
-        const unsigned long long base = (unsigned long long)id + (unsigned long long)a.n * (4ULL * a.call);
-        double u[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            u[r] = (double)r48_element(a.x0, base + (unsigned long long)a.n * r) * (1.0 / 281474976710656.0);
-        const double ra = sqrt(-2.0 * log(1.0 - u[0])), rb = sqrt(-2.0 * log(1.0 - u[2]));
-        const double ph = 6.283185307179586 * u[1], ph2 = 6.283185307179586 * u[3];
-        const double v[3] = {a.scale * ra * cos(ph), a.scale * ra * sin(ph), a.scale * rb * cos(ph2)};
-        double *o = a.obs + (size_t)i * 8;
-        o[0] = v[0]; o[1] = v[1]; o[2] = v[2];
+        double v[3];
+        thermo_velocity(a, id, v);
+        if (a.obs) {
+            double *o = a.obs + (size_t)i * 8;
+            o[0] = v[0]; o[1] = v[1]; o[2] = v[2];
+        }
         acc[0] += v[0]; acc[1] += v[1]; acc[2] += v[2];
         acc[3] += v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     }
@@ -161,8 +177,16 @@ __global__ void __launch_bounds__(256) k_thermo_apply(const ThermoArgs a)
     const double ss = tot[3] - n * (mean[0] * mean[0] + mean[1] * mean[1] + mean[2] * mean[2]);
     const double f = sqrt(a.temperature / (a.mass * ss / (3.0 * n)));
     const int i = a.off + k;
-    const double *o = a.obs + (size_t)i * 8;
-    const double v[3] = {(o[0] - mean[0]) * f, (o[1] - mean[1]) * f, (o[2] - mean[2]) * f};
+    double w[3];
+    if (a.obs) {
+        const double *o = a.obs + (size_t)i * 8;
+        w[0] = o[0]; w[1] = o[1]; w[2] = o[2];
+    } else { // allocation-free form: the same draw again (a pure function of the id)
+        const int id = a.A.meta[i].w;
+        if (id < 0 || id >= a.n) return;
+        thermo_velocity(a, id, w);
+    }
+    const double v[3] = {(w[0] - mean[0]) * f, (w[1] - mean[1]) * f, (w[2] - mean[2]) * f};
     State<P> st;
     st.load(a.A, i);
     if constexpr (P == PREC_FP32) {
@@ -191,6 +215,44 @@ hipError_t launch_thermostat(int prec, const ThermoArgs &a, hipStream_t s)
     default: hipLaunchKernelGGL((k_thermo_apply<PREC_FP64>), dim3(grid), dim3(256), 0, s, a); break;
     }
     LAUNCH_CHECK();
+}
+
+// ------------------------------------------- allocation-free thermostat
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops): the chunk partial sums of md_thermostat_noalloc live
+// in this file-scope device array instead of the pool's workspace, and the
+// drawn velocities are not stored at all (they are drawn again when
+// applied).  Each GPU holds its own copy; host code must use the address
+// hipGetSymbolAddress returns for the current device, never the array's
+// name.  Every chunk row a call reads was written by the same call, so
+// nothing needs clearing; calls that overlap on one GPU race on it.
+static __device__ __align__(256) double scratch[THERMO_SCRATCH_CHUNKS * 8];
+
+#define THERMO_MAX_DEVICES 64
+static double *scratch_ptr[THERMO_MAX_DEVICES];
+static std::mutex scratch_mutex;
+
+hipError_t thermo_scratch_init(int dev)
+{
+    if (dev < 0 || dev >= THERMO_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (scratch_ptr[dev]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev) return hipErrorInvalidDevice; // must be called with that device current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = (double *)p;
+    return hipSuccess;
+}
+
+double *thermo_scratch(int dev)
+{
+    if (dev < 0 || dev >= THERMO_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    return scratch_ptr[dev];
 }
 
 // ------------------------------------------------------------ k_ds_eval

@@ -117,6 +117,7 @@ struct ScaleArgs {
 struct ThermoArgs {
     KArena A;
     double *obs;      // per-slot scratch rows (8 doubles); velocities drawn here
+                      // (nullptr: drawn again when applied, nothing stored)
     double *partial;  // chunk partial sums (8 doubles per chunk)
     int off, n, chunk0, nchunk, remove_mean, pad0;
     unsigned long long x0; // rand48 state of the seed (stream element 0)
@@ -126,6 +127,11 @@ struct ThermoArgs {
 };
 
 hipError_t launch_thermostat(int prec, const ThermoArgs &a, hipStream_t s);
+// Chunk rows of the allocation-free thermostat's scratch array (aux_kernels.hip):
+// at most THERMO_SCRATCH_CHUNKS chunks of 4096 particles per call.
+#define THERMO_SCRATCH_CHUNKS 16384
+hipError_t thermo_scratch_init(int dev); // once per device, with that device current
+double *thermo_scratch(int dev);         // its device address (nullptr before init)
 hipError_t launch_step(int prec, const StepArgs &a, int block, bool obs, hipStream_t s);
 hipError_t launch_count(int prec, const CountArgs &a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);

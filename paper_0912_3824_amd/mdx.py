@@ -38,6 +38,7 @@ EXPORTS = [
     "md_set_launch", "md_ds_eval", "md_strerror", "md_last_error",
     "md_abi_version", "md_tcf_workspace_bytes", "md_tcf_create", "md_tcf_sample",
     "md_tcf_read", "md_tcf_destroy", "md_thermostat", "md_cell_order",
+    "md_thermostat_noalloc",
 ]
 
 CELL_ORDERS = {"row": 0, "morton": 1, "hilbert": 2}
@@ -147,6 +148,7 @@ def load():
         "md_tcf_read": (i32, [vp, i64p, dp, i64p]),
         "md_tcf_destroy": (None, [vp]),
         "md_thermostat": (i32, [vp, i32, ctypes.c_double, ctypes.c_uint64, i64, i32]),
+        "md_thermostat_noalloc": (i32, [vp, i32, ctypes.c_double, ctypes.c_uint64, i64, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -316,6 +318,14 @@ class MdSystem:
         velocities from the leap-frogged rand48 stream, rescaled to exactly T."""
         self._check(self.lib.md_thermostat(self.h, int(slot), float(temperature), int(seed) & (2 ** 64 - 1),
                                            int(call), 1 if remove_mean else 0), "md_thermostat")
+
+    def thermostat_noalloc(self, slot: int, temperature: float, seed: int, call: int,
+                           remove_mean: bool = True):
+        """md_thermostat_noalloc: the same call with its scratch in the
+        library's static device array (allocates nothing)."""
+        self._check(self.lib.md_thermostat_noalloc(self.h, int(slot), float(temperature),
+                                                   int(seed) & (2 ** 64 - 1), int(call),
+                                                   1 if remove_mean else 0), "md_thermostat_noalloc")
 
     def andersen(self, slot: int, temperature: float, mu: float, steps: int, seed: int, first_call: int = 0):
         """Advance `steps` steps with the heat bath of collision rate mu: a

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     lib = mdx.load()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.md_abi_version() == 3
+    assert lib.md_abi_version() == 4
 
 
 def _cfg(prec="ds", **kw):

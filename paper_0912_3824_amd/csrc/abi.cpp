@@ -720,6 +720,20 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     r.sc = (float)(h.L / 4294967296.0);
     r.L_hi = (float)h.L;
     r.L_lo = (float)(h.L - (double)r.L_hi);
+    {   // pair constants in fixed-point units (see RepDev)
+        const PairDev &p = s->pp;
+        const double u = (double)r.sc;
+        const double iu2 = 1.0 / (u * u);
+        for (int t = 0; t < 4; ++t) {
+            r.rc2s[t] = (float)(p.rc2d[t] * iu2);
+            r.sig2s[t] = (float)(p.sig2d[t] * iu2);
+            r.e24s[t] = (float)(p.eps24d[t] / u);
+            r.rcs[t] = (float)(p.rcd[t] / u);
+            r.xsc[t] = p.smooth ? (float)(u / p.hsd[t]) : 0.0f;
+            r.ihs[t] = p.smooth ? (float)(1.0 / p.hsd[t]) : 0.0f;
+        }
+        r.hs2s = (float)(p.hs2d / (u * u));
+    }
     r.items3 = h.nd * h.nd * h.nd; // a sort work item covers a cell in every plane
     r.items4 = items4_of(s, h.n, h.nd);
     build_shape(s, h.n, h.nd, r.bparts, r.blanes);

@@ -50,6 +50,12 @@ struct RepDev {
     int items3, items4; // work items of the sort and list-build kernels
     int bparts;   // list-build work items per row segment (its members split evenly)
     int blanes;   // lanes building one member's list; 0 = chosen per work item
+    // pair constants in fixed-point units u = L / 2^32, per species pair
+    // [si*2+sj]: rc^2/u^2, sigma^2/u^2, 24 eps/u; smoothing: rc/u, u/(h sigma),
+    // 1/(h sigma); and (skin/2)^2/u^2 for the displacement test
+    float rc2s[4], sig2s[4], e24s[4], rcs[4], xsc[4], ihs[4];
+    float hs2s;
+    int pad0;
 };
 
 // Control word of a slot: x = completed steps, y = 1 if velocities are at a

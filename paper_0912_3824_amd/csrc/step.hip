@@ -116,7 +116,8 @@ __device__ __forceinline__ uint4 snap_of(const StateD &s, const RepDev &r, uint3
 
 // ------------------------------------------------ pair constants per lane
 // Scaled units: separations in fixed-point units u = L / 2^32.  With
-// r2s = r^2 / u^2 the pair term needs rc^2/u^2, sigma^2/u^2 and 24 eps / u.
+// r2s = r^2 / u^2 the pair term needs rc^2/u^2, sigma^2/u^2 and 24 eps / u;
+// the host precomputes them per replica (RepDev).
 struct LaneConsts {
     float rc2s[2], sig2s[2], e24s[2];
     // smoothing (Sec. 4): rc in fixed-point units, u/(h sigma), 1/(h sigma),
@@ -127,17 +128,15 @@ struct LaneConsts {
 __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, const RepDev &r)
 {
     LaneConsts c;
-    double u = (double)r.sc;
-    double iu2 = 1.0 / (u * u);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-        int t = si * 2 + b;
-        c.rc2s[b] = (float)(pp.rc2d[t] * iu2);
-        c.sig2s[b] = (float)(pp.sig2d[t] * iu2);
-        c.e24s[b] = (float)(pp.eps24d[t] / u);
-        c.rcs[b] = (float)(pp.rcd[t] / u);
-        c.xsc[b] = pp.smooth ? (float)(u / pp.hsd[t]) : 0.0f;
-        c.ihs[b] = pp.smooth ? (float)(1.0 / pp.hsd[t]) : 0.0f;
+        const int t = si * 2 + b;
+        c.rc2s[b] = r.rc2s[t];
+        c.sig2s[b] = r.sig2s[t];
+        c.e24s[b] = r.e24s[t];
+        c.rcs[b] = r.rcs[t];
+        c.xsc[b] = r.xsc[t];
+        c.ihs[b] = r.ihs[t];
         c.e4[b] = pp.eps4[t];
         c.sh[b] = pp.shift[t];
     }
@@ -509,8 +508,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         uint4 R = A.xref[i];
         float dx = (float)(int)(X.x - R.x), dy = (float)(int)(X.y - R.y), dz = (float)(int)(X.z - R.z);
         float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        float thr = (float)(a.pp.hs2d / ((double)rp.sc * (double)rp.sc));
-        far = d2 > thr;
+        far = d2 > rp.hs2s;
         if constexpr (P == PREC_FP32) bad = !isfinite(st.x + st.y + st.z);
         else if constexpr (P == PREC_DS) bad = !isfinite(st.x.hi + st.y.hi + st.z.hi);
         else bad = !isfinite(st.x + st.y + st.z);

@@ -123,22 +123,26 @@ struct LaneConsts {
     // smoothing (Sec. 4): rc in fixed-point units, u/(h sigma), 1/(h sigma),
     // 4 eps and the energy shift
     float rcs[2], xsc[2], ihs[2], e4[2], sh[2];
+    float e24[2]; // 24 eps (unscaled, for the virial)
 };
 
 __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, const RepDev &r)
 {
+    // constant indices and selects on si: an index computed from si would
+    // put the replica record in scratch memory
     LaneConsts c;
+    const bool b1 = si != 0;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-        const int t = si * 2 + b;
-        c.rc2s[b] = r.rc2s[t];
-        c.sig2s[b] = r.sig2s[t];
-        c.e24s[b] = r.e24s[t];
-        c.rcs[b] = r.rcs[t];
-        c.xsc[b] = r.xsc[t];
-        c.ihs[b] = r.ihs[t];
-        c.e4[b] = pp.eps4[t];
-        c.sh[b] = pp.shift[t];
+        c.rc2s[b] = b1 ? r.rc2s[2 + b] : r.rc2s[b];
+        c.sig2s[b] = b1 ? r.sig2s[2 + b] : r.sig2s[b];
+        c.e24s[b] = b1 ? r.e24s[2 + b] : r.e24s[b];
+        c.rcs[b] = b1 ? r.rcs[2 + b] : r.rcs[b];
+        c.xsc[b] = b1 ? r.xsc[2 + b] : r.xsc[b];
+        c.ihs[b] = b1 ? r.ihs[2 + b] : r.ihs[b];
+        c.e4[b] = b1 ? pp.eps4[2 + b] : pp.eps4[b];
+        c.sh[b] = b1 ? pp.shift[2 + b] : pp.shift[b];
+        c.e24[b] = b1 ? pp.eps24[2 + b] : pp.eps24[b];
     }
     return c;
 }
@@ -200,14 +204,14 @@ __device__ __forceinline__ void entry_fixed(uint4 xi, uint4 xj, const LaneConsts
     fs = in ? fs : 0.0f;
     acc.add(fs, dx, dy, dz, ix, iy, iz);
     if (EN) {
-        const int tt = si * 2 + (b ? 1 : 0);
+        const float e24u = b ? c.e24[1] : c.e24[0], e4u = b ? c.e4[1] : c.e4[0], shu = b ? c.sh[1] : c.sh[0];
         if (in) {
             if (KIND == PK_SMOOTH) {
                 e_sum += 0.5 * (double)(vts * g);
-                w_sum += 0.5 * (double)(g * pp.eps24[tt] * s6 * t - vts * dgr);
+                w_sum += 0.5 * (double)(g * e24u * s6 * t - vts * dgr);
             } else {
-                e_sum += 0.5 * ((double)(pp.eps4[tt] * s6 * (s6 - 1.0f)) - (double)pp.shift[tt]);
-                w_sum += 0.5 * (double)(pp.eps24[tt] * s6 * t);
+                e_sum += 0.5 * ((double)(e4u * s6 * (s6 - 1.0f)) - (double)shu);
+                w_sum += 0.5 * (double)(e24u * s6 * t);
             }
         }
     }

@@ -470,13 +470,13 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
 #pragma unroll 1
     for (int v = 0; v < nvis; ++v) scan_cell(nd == 1 ? 0 : visit_cell(v, lx_m, full, nd, NX));
     const int last_cell = nd == 1 ? 0 : visit_cell(26, lx_m, full, nd, NX);
-    // Pad the list to a multiple of 8 with a particle that is outside the
+    // Pad the list to a multiple of 4 with a particle that is outside the
     // list radius at this build: it stays beyond the force cutoff until the
     // next build (each particle moves at most skin/2), so the force loop
     // needs no per-entry validity test.  The pad is the first rejected
     // candidate of the last cell visited (a corner cell), else of any
     // staged cell.
-    if (cnt & 7) {
+    if (cnt & 3) {
         int pad = -1;
         for (int k = 0, kk = last_cell; k <= T.ncell && pad < 0; kk = k++) {
             const int4 c = T.pk[kk];
@@ -487,7 +487,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             }
         }
         if (pad < 0) atomicOr(a.status + s, 8);
-        for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
+        for (int k = cnt; k < ((cnt + 3) & ~3) && k < cap; ++k)
             col[(size_t)(k >> 2) * row_stride + (k & 3)] = list_entry(pad < 0 ? i : pad);
     }
     A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
@@ -586,9 +586,9 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
 #pragma unroll 1
     for (int v = 0; v < nvis; ++v) scan_cell(nd == 1 ? 0 : visit_cell(v, lx_m, full, nd, NX));
     const int last_cell = nd == 1 ? 0 : visit_cell(26, lx_m, full, nd, NX);
-    // pad to a multiple of 8, as in the one-lane build: the first rejected
+    // pad to a multiple of 4, as in the one-lane build: the first rejected
     // candidate of the last visited cell, else (rare) of any staged cell
-    if (cnt & 7) {
+    if (cnt & 3) {
         int pad = -1;
         {
             const int4 cl = T.pk[last_cell];
@@ -611,7 +611,7 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
                 }
             }
             if (pad < 0) atomicOr(a.status + s, 8);
-            for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k)
+            for (int k = cnt; k < ((cnt + 3) & ~3) && k < cap; ++k)
                 col[(size_t)(k >> 2) * row_stride + (k & 3)] = list_entry(pad < 0 ? i : pad);
         }
     }

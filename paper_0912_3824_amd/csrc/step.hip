@@ -224,36 +224,37 @@ __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int e)
     return *(const uint4 *)((const char *)snap + (uint32_t)e);
 }
 
-// Force (and optionally energy/virial) on particle i from its list.  The
-// loop is software-pipelined over blocks of four entries with two register
-// buffers: while one block is computed, the snapshots of the next block and
-// the indices of the block after it are in flight.  Lists are padded to a
-// multiple of eight valid entries by the list build and row indices are clamped, so every
-// prefetch is unconditional and no control-flow join forces the memory
-// counters to drain inside the loop.
+// Force (and optionally energy/virial) on particle i from its list.  Lists
+// are padded to a multiple of four entries; lane `sub` of the particle's
+// `lpp` lanes takes blocks sub, sub + lpp, sub + 2 lpp, ... of four entries,
+// two of them per iteration of a software-pipelined loop (while one block
+// is computed, the snapshots of the next and the indices of the one after
+// it are in flight), and an odd last block after it.  Row indices are
+// clamped, so every prefetch is unconditional and no control-flow join
+// forces the memory counters to drain inside the loop.
 template <int P, bool EN, int KIND>
 __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
                                             uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
                                             FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp)
 {
     const int cnt = A.nbr_cnt[i];
-    const int nq = ((cnt + 7) >> 3) << 1; // blocks of four, padded to an even count
+    const int nq = (cnt + 3) >> 2; // blocks of four (a partial block is completed by padding)
     acc.init();
-    const int npair = nq >> 1;            // this lane takes pairs sub, sub + lpp, ...
-    if (sub >= npair) return;
+    if (sub >= nq) return;
     const int last = nq - 1;
-    int p = sub;
-    // indices two blocks ahead, snapshots one block ahead
-    int4 ja = list_row(A, i, 2 * p), jb = list_row(A, i, 2 * p + 1);
-    uint4 a0 = ld_snap(snap, ja.x), a1 = ld_snap(snap, ja.y), a2 = ld_snap(snap, ja.z),
-          a3 = ld_snap(snap, ja.w);
-    ja = list_row(A, i, min(2 * (p + lpp), last));
-    for (; p < npair; p += lpp) {
+    const int nb = (nq - sub + lpp - 1) / lpp; // this lane's blocks
+    auto row = [&](int k) { return list_row(A, i, min(sub + k * lpp, last)); };
+    // block k's snapshots in a, indices of block k+1 in jb and of k+2 in ja
+    int4 ja = row(0), jb = row(1);
+    uint4 a0 = ld_snap(snap, ja.x), a1 = ld_snap(snap, ja.y), a2 = ld_snap(snap, ja.z), a3 = ld_snap(snap, ja.w);
+    ja = row(2);
+    int k = 0;
+    for (; k + 1 < nb; k += 2) {
         // (the scheduling barriers keep each batch of loads ahead of the
         // block computed while it is in flight)
         const uint4 b0 = ld_snap(snap, jb.x), b1 = ld_snap(snap, jb.y), b2 = ld_snap(snap, jb.z),
                     b3 = ld_snap(snap, jb.w);
-        jb = list_row(A, i, min(2 * (p + lpp) + 1, last));
+        jb = row(k + 3);
         __builtin_amdgcn_sched_barrier(0);
         entry_fixed<P, EN, KIND>(xi, a0, c, pp, si, acc, e_sum, w_sum);
         entry_fixed<P, EN, KIND>(xi, a1, c, pp, si, acc, e_sum, w_sum);
@@ -264,13 +265,19 @@ __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__rest
         a1 = ld_snap(snap, ja.y);
         a2 = ld_snap(snap, ja.z);
         a3 = ld_snap(snap, ja.w);
-        ja = list_row(A, i, min(2 * (p + 2 * lpp), last));
+        ja = row(k + 4);
         __builtin_amdgcn_sched_barrier(0);
         entry_fixed<P, EN, KIND>(xi, b0, c, pp, si, acc, e_sum, w_sum);
         entry_fixed<P, EN, KIND>(xi, b1, c, pp, si, acc, e_sum, w_sum);
         entry_fixed<P, EN, KIND>(xi, b2, c, pp, si, acc, e_sum, w_sum);
         entry_fixed<P, EN, KIND>(xi, b3, c, pp, si, acc, e_sum, w_sum);
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if (k < nb) { // an odd last block, already loaded
+        entry_fixed<P, EN, KIND>(xi, a0, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a1, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a2, c, pp, si, acc, e_sum, w_sum);
+        entry_fixed<P, EN, KIND>(xi, a3, c, pp, si, acc, e_sum, w_sum);
     }
 }
 

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 4
+#define MD_ABI_VERSION 5
 
 typedef struct md_system md_system;
 
@@ -134,6 +134,19 @@ typedef struct {
                               shifted potential times g(x) = x^4 / (1 + x^4),
                               x = (r - rc_ab) / (h sigma_ab); 0 = no smoothing;
                               >= 0 and finite.  (WCA is rcut = 2^(1/6) sigma.) */
+    int32_t rebuild_every; /* 0, or K >= 2: a replica also rebuilds its lists after
+                              a step whose count is a multiple of K once its largest
+                              displacement since the last build exceeds
+                              rebuild_early * skin / 2 (besides the skin / 2 rule of
+                              Sec. 2.2).  Replicas of a pool whose step counts are
+                              aligned then rebuild together, at a few launches, so a
+                              batch pays the rebuild kernels' latency once for many
+                              replicas.  The rule reads only the replica's own state
+                              (a replica rebuilds at the same steps alone and in a
+                              pool); it is part of the arithmetic (it moves the
+                              rebuild steps, hence the sort and sum order). */
+    int32_t reserved0;
+    double rebuild_early;  /* the fraction in (0, 1] for rebuild_every; else ignored */
 } md_config;
 
 /* One replica: N particles in a cubic box of edge `box`. */

@@ -24,7 +24,7 @@ namespace {
 
 constexpr int64_t ALIGN = 256;
 constexpr uint32_t CKPT_MAGIC = 0x4d445843; // "MDXC"
-constexpr int CKPT_VERSION = 2;
+constexpr int CKPT_VERSION = 3;
 constexpr int MD_DEFAULT_LPP = 2;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -184,6 +184,10 @@ static md_status validate_cfg(const md_config *c, std::string *why)
         c->lanes_per_particle != 4)
         return bad("lanes_per_particle must be 0, 1, 2 or 4");
     if (!(c->smooth >= 0) || !std::isfinite(c->smooth)) return bad("smooth must be >= 0 and finite");
+    if (c->rebuild_every != 0 && (c->rebuild_every < 2 || c->rebuild_every > 1000000))
+        return bad("rebuild_every must be 0 or in [2, 1e6]");
+    if (c->rebuild_every != 0 && !(c->rebuild_early > 0 && c->rebuild_early <= 1))
+        return bad("rebuild_early must be in (0, 1] when rebuild_every is set");
     if (c->cell_order != MD_ORDER_ROW && c->cell_order != MD_ORDER_MORTON && c->cell_order != MD_ORDER_HILBERT)
         return bad("cell_order must be MD_ORDER_ROW, MD_ORDER_MORTON or MD_ORDER_HILBERT");
     return MD_OK;
@@ -298,6 +302,8 @@ static void make_tables(md_system *s)
     }
     p.hs2d = 0.25 * c->skin * c->skin;
     p.hs2 = (float)p.hs2d;
+    p.align_every = c->rebuild_every;
+    p.hs2d_early = c->rebuild_every ? p.hs2d * c->rebuild_early * c->rebuild_early : p.hs2d;
     p.nsp = c->n_species;
     IntegDev &g = s->ig;
     g.m = c->mass;
@@ -733,6 +739,7 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
             r.ihs[t] = p.smooth ? (float)(1.0 / p.hsd[t]) : 0.0f;
         }
         r.hs2s = (float)(p.hs2d / (u * u));
+        r.hs2s_early = (float)(p.hs2d_early / (u * u));
     }
     r.items3 = h.nd * h.nd * h.nd; // a sort work item covers a cell in every plane
     r.items4 = items4_of(s, h.n, h.nd);
@@ -1559,6 +1566,8 @@ struct CkptHeader {
     int32_t version, precision, n_species, n, NW, NS, nd, lpp;
     double L, dt, skin, mass, eps[4], sigma[4], rcut[4];
     int64_t step, fresh, nreb, status;
+    int64_t rebuild_every;
+    double rebuild_early, smooth;
 };
 
 int64_t md_checkpoint_bytes(md_system *s, int32_t slot)
@@ -1603,6 +1612,9 @@ md_status md_save(md_system *s, int32_t slot, void *blob, int64_t bytes)
     memcpy(H.rcut, s->cfg.rcut, sizeof H.rcut);
     H.step = c.x;
     H.fresh = c.y;
+    H.rebuild_every = s->cfg.rebuild_every;
+    H.rebuild_early = s->cfg.rebuild_every ? s->cfg.rebuild_early : 0.0;
+    H.smooth = s->cfg.smooth;
     H.nreb = nr;
     H.status = stv;
     char *b = (char *)blob;
@@ -1626,7 +1638,8 @@ md_status md_restore(md_system *s, int32_t slot, const void *blob, int64_t bytes
     if (H.magic != CKPT_MAGIC || H.version != CKPT_VERSION) return fail(s, MD_E_ARG, "not a checkpoint");
     if (H.precision != s->prec || H.lpp != s->lpp || H.n_species != s->cfg.n_species || H.dt != s->cfg.dt || H.skin != s->cfg.skin ||
         H.mass != s->cfg.mass || memcmp(H.eps, s->cfg.eps, sizeof H.eps) || memcmp(H.sigma, s->cfg.sigma, sizeof H.sigma) ||
-        memcmp(H.rcut, s->cfg.rcut, sizeof H.rcut))
+        memcmp(H.rcut, s->cfg.rcut, sizeof H.rcut) || H.rebuild_every != s->cfg.rebuild_every ||
+        H.rebuild_early != (s->cfg.rebuild_every ? s->cfg.rebuild_early : 0.0) || H.smooth != s->cfg.smooth)
         return fail(s, MD_E_ARG, "checkpoint from an incompatible pool");
     const int64_t n = H.n;
     if (n < 1 || bytes < (int64_t)sizeof(CkptHeader) + 16 * n * (H.NW + 2 * H.NS + 1))

@@ -55,7 +55,7 @@ struct RepDev {
     // 1/(h sigma); and (skin/2)^2/u^2 for the displacement test
     float rc2s[4], sig2s[4], e24s[4], rcs[4], xsc[4], ihs[4];
     float hs2s;
-    int pad0;
+    float hs2s_early; // (rebuild_early * skin/2)^2 / u^2 (aligned rebuilds)
 };
 
 // Control word of a slot: x = completed steps, y = 1 if velocities are at a
@@ -73,6 +73,8 @@ struct PairDev {
     double rl2d[4], rc2d[4], sig2d[4], eps24d[4], eps4d[4], shiftd[4];
     float hs2;       // (skin/2)^2
     double hs2d;
+    double hs2d_early; // (rebuild_early * skin/2)^2
+    int align_every;   // rebuild_every (0 = off)
     int nsp;
     int uniform;     // 1 if rc_ab / sigma_ab is the same for every pair
     float s2cut;     // then (sigma_ab / rc_ab)^2: a pair is inside iff sigma^2/r^2 > s2cut

@@ -496,9 +496,11 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         return;
     }
 
-    // new snapshot, displacement test, cell count
+    // new snapshot, displacement test (with the lower threshold of an
+    // aligned rebuild step when the pool sets one), cell count
     int cell;
     bool far, bad;
+    const bool aligned = a.pp.align_every > 0 && (ctl.x + 1) % a.pp.align_every == 0;
     if constexpr (P == PREC_FP64) {
         double w = bits_of_meta(meta);
         a.snap_next[i] = dbl2_to_u4(st.x, st.y);
@@ -510,7 +512,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         dx -= rp.L * rint(dx * rp.invL);
         dy -= rp.L * rint(dy * rp.invL);
         dz -= rp.L * rint(dz * rp.invL);
-        far = dx * dx + dy * dy + dz * dz > a.pp.hs2d;
+        far = dx * dx + dy * dy + dz * dz > (aligned ? a.pp.hs2d_early : a.pp.hs2d);
         bad = !isfinite(st.x + st.y + st.z);
         cell = dbl_cell(st.x, st.y, st.z, rp.L, rp.invL, rp.nd);
     } else {
@@ -519,7 +521,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         uint4 R = A.xref[i];
         float dx = (float)(int)(X.x - R.x), dy = (float)(int)(X.y - R.y), dz = (float)(int)(X.z - R.z);
         float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        far = d2 > rp.hs2s;
+        far = d2 > (aligned ? rp.hs2s_early : rp.hs2s);
         if constexpr (P == PREC_FP32) bad = !isfinite(st.x + st.y + st.z);
         else if constexpr (P == PREC_DS) bad = !isfinite(st.x.hi + st.y.hi + st.z.hi);
         else bad = !isfinite(st.x + st.y + st.z);

@@ -52,7 +52,9 @@ class MdConfig(ctypes.Structure):
                 ("nbr_capacity", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("max_particles", ctypes.c_int64), ("max_cells", ctypes.c_int64),
                 ("max_density", ctypes.c_double), ("lanes_per_particle", ctypes.c_int32),
-                ("cell_order", ctypes.c_int32), ("smooth", ctypes.c_double)]
+                ("cell_order", ctypes.c_int32), ("smooth", ctypes.c_double),
+                ("rebuild_every", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("rebuild_early", ctypes.c_double)]
 
 
 class MdReplica(ctypes.Structure):
@@ -169,7 +171,8 @@ def _ip(a: np.ndarray):
 def make_config(table, precision, dt: float, skin: float, max_slots: int,
                 max_particles: int, mass: float = 1.0, nbr_capacity: int = 0,
                 max_cells: int = 0, max_density: float = 0.0,
-                lanes_per_particle: int = 0, cell_order="row") -> MdConfig:
+                lanes_per_particle: int = 0, cell_order="row", rebuild_every: int = 0,
+                rebuild_early: float = 0.0) -> MdConfig:
     """md_config from a pair table (md_inputs.PairTable, including its
     smoothing width) and run parameters."""
     if isinstance(precision, str):
@@ -191,6 +194,8 @@ def make_config(table, precision, dt: float, skin: float, max_slots: int,
     c.lanes_per_particle = int(lanes_per_particle)
     c.smooth = float(getattr(table, "smooth", 0.0))
     c.cell_order = CELL_ORDERS[cell_order] if isinstance(cell_order, str) else int(cell_order)
+    c.rebuild_every = int(rebuild_every)
+    c.rebuild_early = float(rebuild_early)
     return c
 
 

@@ -51,37 +51,45 @@ def _timed_step(pool, steps):
     return time.perf_counter() - t0
 
 
-def batch(n_rep=256, steps=2000, warmup=200, alone_sample=16, precision="ds", seed=20240101):
+def batch(n_rep=256, steps=2000, warmup=200, alone_sample=16, precision="ds", seed=20240101,
+          rebuild_every=0, rebuild_early=0.0, skin=None, shape=None):
     import md_inputs as I
     from paper_0912_3824_amd import mdx, tune
     reps = I.make_ka_ensemble(n_rep, seed=seed)
     total = sum(r.n for r in reps)
-    pool = mdx.md_init(reps, precision)
+    kw = dict(rebuild_every=rebuild_every, rebuild_early=rebuild_early, skin=skin)
+    pool = mdx.md_init(reps, precision, **kw)
     tune.apply_cached(pool)
+    if shape:
+        pool.set_launch(**shape)
     pool.step(warmup)
     t = _timed_step(pool, steps)
     obs = pool.observables()
     assert not any(o["status"] for o in obs if o["n"])
     prof = pool.profile_steps(100)
+    pool_shape = pool.get_launch()
     pool.close()
     batched = total * steps / t
     log(f"batch: {n_rep} replicas, {total} particles, {t / steps * 1e6:.1f} us/step, {batched:.4g} p-s/s")
     rng = np.random.default_rng(1)
-    idx = np.sort(rng.choice(n_rep, size=min(alone_sample, n_rep), replace=False))
+    idx = np.sort(rng.choice(n_rep, size=min(alone_sample, n_rep), replace=False)) if alone_sample > 0 else []
     work, wall = 0, 0.0
     for k in idx:
-        p = mdx.md_init([reps[k]], precision)
+        p = mdx.md_init([reps[k]], precision, **kw)
         p.step(warmup)
         dt = _timed_step(p, steps)
         work += reps[k].n * steps
         wall += dt
         p.close()
-    alone = work / wall
-    log(f"alone (sample of {len(idx)}): {alone:.4g} p-s/s")
+    alone = work / wall if wall > 0 else None
+    if alone:
+        log(f"alone (sample of {len(idx)}): {alone:.4g} p-s/s")
     return {"replicas": n_rep, "particles": total, "steps": steps, "precision": precision,
+            "rebuild_every": rebuild_every, "rebuild_early": rebuild_early, "skin": skin,
+            "shape": pool_shape,
             "batched_particle_steps_per_s": batched, "batched_us_per_step": t / steps * 1e6,
             "alone_particle_steps_per_s": alone, "alone_sample": int(len(idx)),
-            "speedup_vs_alone": batched / alone, "step_kernel_ms": prof["step_kernel_ms"],
+            "speedup_vs_alone": batched / alone if alone else None, "step_kernel_ms": prof["step_kernel_ms"],
             "rebuild_group_ms_mean": prof["rebuild_ms_mean"]}
 
 
@@ -218,9 +226,16 @@ if __name__ == "__main__":
     ap.add_argument("--steps-lo", type=int, default=1000)
     ap.add_argument("--steps-hi", type=int, default=10000)
     ap.add_argument("--precision", default="ds")
+    ap.add_argument("--rebuild-every", type=int, default=0, help="aligned list rebuilds (md_config)")
+    ap.add_argument("--rebuild-early", type=float, default=0.0)
+    ap.add_argument("--skin", type=float, default=None)
+    ap.add_argument("--alone-sample", type=int, default=16)
+    ap.add_argument("--shape", default=None, help="launch shape as JSON (md_launch fields)")
     a = ap.parse_args()
     if a.mode == "batch":
-        r = batch(a.replicas, a.steps, precision=a.precision)
+        r = batch(a.replicas, a.steps, precision=a.precision, rebuild_every=a.rebuild_every,
+                  rebuild_early=a.rebuild_early, skin=a.skin, alone_sample=a.alone_sample,
+                  shape=json.loads(a.shape) if a.shape else None)
     elif a.mode == "tcf":
         r = tcf(steps=a.steps, precision=a.precision)
     elif a.mode == "thermo":

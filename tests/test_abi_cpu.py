@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     lib = mdx.load()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.md_abi_version() == 4
+    assert lib.md_abi_version() == 5
 
 
 def _cfg(prec="ds", **kw):
@@ -71,3 +71,11 @@ def test_create_rejects_missing_workspace_without_gpu():
     h = ctypes.c_void_p()
     assert lib.md_create(ctypes.byref(c), None, 0, None, ctypes.byref(h)) == -3
     assert lib.md_create(ctypes.byref(c), ctypes.c_void_p(0x1001), 1 << 40, None, ctypes.byref(h)) == -3
+
+
+def test_aligned_rebuild_settings_are_validated():
+    ok = _cfg(rebuild_every=8, rebuild_early=0.5)
+    assert mdx.md_validate(ok) == 0
+    for k, e in [(1, 0.5), (-2, 0.5), (8, 0.0), (8, 1.5)]:
+        assert mdx.md_validate(_cfg(rebuild_every=k, rebuild_early=e)) == -1, (k, e)
+    assert mdx.md_validate(_cfg(rebuild_every=0, rebuild_early=0.0)) == 0

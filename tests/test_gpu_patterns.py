@@ -31,23 +31,53 @@ def _reps():
     return out
 
 
-@pytest.mark.parametrize("prec", ["ds", "fp32", "fp64"])
-def test_batched_replicas_equal_alone(prec):
+@pytest.mark.parametrize("prec,align", [("ds", 0), ("fp32", 0), ("fp64", 0), ("ds", 8), ("fp64", 4)])
+def test_batched_replicas_equal_alone(prec, align):
     """Replicas of uneven N advanced together by one pool are bitwise equal to
-    the same replicas advanced alone (incl. one in single-cell mode)."""
+    the same replicas advanced alone (incl. one in single-cell mode), also
+    with aligned rebuilds (a replica's rebuild steps depend on its own state
+    only)."""
     reps = _reps()
-    say("batched vs alone", prec)
-    pool = pool_for(reps, prec)
+    kw = dict(rebuild_every=align, rebuild_early=0.6) if align else {}
+    say("batched vs alone", prec, "aligned rebuilds every", align)
+    pool = pool_for(reps, prec, **kw)
     pool.step(300)
     batched = [_state(pool, k) for k in range(len(reps))]
     obs = pool.observables()
     assert all(o["n_rebuilds"] >= 2 for o in obs[:len(reps)])
     pool.close()
     for k, s in enumerate(reps):
-        alone = pool_for([s], prec)
+        alone = pool_for([s], prec, **kw)
         alone.step(300)
         assert _same(_state(alone), batched[k]), k
         alone.close()
+
+
+def test_aligned_rebuilds_happen_at_multiples_and_follow_the_oracle():
+    """With rebuild_every = 8 the rebuilds of a replica (counted per step)
+    fall on multiples of 8 unless the skin/2 rule forces one earlier, and the
+    trajectory stays within the oracle's tolerance (rebuilding early only
+    moves list builds)."""
+    from oracle import oracle as O
+    from oracle.upload import state_after_upload
+    s = I.make_ka(3001, 1.0, jitter=0.1, seed=4)
+    pool = pool_for([s], "ds", rebuild_every=8, rebuild_early=0.5)
+    steps_at, last = [], pool.observables()[0]["n_rebuilds"]
+    for k in range(1, 201):
+        pool.step(1)
+        nr = pool.observables()[0]["n_rebuilds"]
+        if nr != last:
+            steps_at.append(k)
+            last = nr
+    say("aligned rebuild steps", steps_at)
+    assert len(steps_at) >= 4
+    assert sum(1 for k in steps_at if k % 8 == 0) >= 0.75 * len(steps_at)
+    p1, v1, i1 = pool.get_state(0)
+    p0, v0, i0 = state_after_upload(s.pos, s.vel, s.box, "ds")
+    pr, vr, ir, _ = O.vv(p0, v0, s.box, s.species, s.table, s.dt, 200)
+    d = np.abs((p1 + i1 * s.box) - (pr + (ir + i0) * s.box)).max()
+    assert d < 1e-4
+    pool.close()
 
 
 def test_graph_eager_shapes_and_split_calls_are_bitwise_equal():

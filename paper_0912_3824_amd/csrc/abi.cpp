@@ -563,14 +563,18 @@ static md_status launch_one_step(md_system *s, int p)
     return launch_rebuild(s, p, -1, true);
 }
 
-static md_status get_graph(md_system *s, int steps, hipGraphExec_t *out)
+// The launches of `steps` consecutive steps starting at snapshot parity
+// `parity`, captured once into a hipGraph and cached by (steps, parity).
+static md_status get_graph(md_system *s, int steps, int parity, hipGraphExec_t *out)
 {
-    auto it = s->graphs.find(steps);
+    const int key = 2 * steps + parity;
+    auto it = s->graphs.find(key);
     if (it != s->graphs.end()) { *out = it->second; return MD_OK; }
+    if (s->graphs.size() >= 64) drop_graphs(s); // callers cycling through many step counts
     hipGraph_t g = nullptr;
     HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     md_status st = MD_OK;
-    for (int k = 0; k < steps && st == MD_OK; ++k) st = launch_one_step(s, k & 1);
+    for (int k = 0; k < steps && st == MD_OK; ++k) st = launch_one_step(s, (parity + k) & 1);
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (st != MD_OK) { if (g) (void)hipGraphDestroy(g); return st; }
     if (e != hipSuccess) return fail(s, MD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -578,29 +582,32 @@ static md_status get_graph(md_system *s, int steps, hipGraphExec_t *out)
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(s, MD_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    s->graphs[steps] = ex;
+    s->graphs[key] = ex;
     *out = ex;
     return MD_OK;
 }
 
+// n step launches: replays of graphs of graph_steps launches, the remainder
+// (however short) as one more captured graph; eager launches when graphs
+// are off.
 static md_status run_launches(md_system *s, int64_t n)
 {
     const int G = s->launch.graph_steps;
     while (n > 0) {
-        if (G >= 2 && n >= G && s->parity == 0) {
-            hipGraphExec_t ex;
-            md_status st = get_graph(s, G, &ex);
+        if (G < 2) {
+            md_status st = launch_one_step(s, s->parity);
             if (st != MD_OK) return st;
-            while (n >= G) {
-                HIPCHK(s, hipGraphLaunch(ex, s->stream));
-                n -= G;
-            }
+            s->parity ^= 1;
+            --n;
             continue;
         }
-        md_status st = launch_one_step(s, s->parity);
+        const int k = (int)std::min<int64_t>(n, G);
+        hipGraphExec_t ex;
+        md_status st = get_graph(s, k, s->parity, &ex);
         if (st != MD_OK) return st;
-        s->parity ^= 1;
-        --n;
+        HIPCHK(s, hipGraphLaunch(ex, s->stream));
+        n -= k;
+        s->parity ^= k & 1;
     }
     return MD_OK;
 }
@@ -1183,6 +1190,9 @@ md_status md_rebuild_neighbours(md_system *s)
 {
     if (!s) return MD_E_ARG;
     const int p = s->parity, kp = p ^ 1;
+    // the re-sort moves particles between slots: forces stored by slot are void
+    for (int k = 0; k < (int)s->lay.slots; ++k)
+        if (s->slots[k].attached) HIPCHK(s, launch_poke((int *)(s->ctl[p] + k) + 3, 0, s->stream));
     HIPCHK(s, hipMemsetAsync(s->count[kp], 0, 4 * s->lay.cells, s->stream));
     CountArgs ca;
     memset(&ca, 0, sizeof ca);
@@ -1364,6 +1374,8 @@ md_status md_thermostat(md_system *s, int32_t slot, double temperature, uint64_t
     a.mass = s->cfg.mass;
     a.scale = std::sqrt(temperature / s->cfg.mass);
     HIPCHK(s, launch_thermostat(s->prec, a, s->stream));
+    // the draws went through the scratch rows that hold stored forces
+    HIPCHK(s, launch_poke((int *)(s->ctl[s->parity] + slot) + 3, 0, s->stream));
     return MD_OK;
 }
 

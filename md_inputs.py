@@ -199,22 +199,32 @@ def make_ka_ensemble(n_rep: int = 256, n_lo: int = 500, n_hi: int = 8000,
 
 @dataclasses.dataclass
 class Job:
-    """A trajectory job of the serving trace."""
+    """A trajectory job of the serving trace.  A job with tcf_every > 0 also
+    asks for time-correlation functions (Sec. 2.5 blocking scheme: levels of
+    tcf_block entries, a sample every tcf_every steps, wave number tcf_q)."""
     job_id: int
     arrival: float      # seconds after trace start
     n: int
     steps: int
     temperature: float
     seed: int
+    tcf_every: int = 0
+    tcf_levels: int = 4
+    tcf_block: int = 10
+    tcf_q: float = 7.25
 
 
 def serving_trace(n_jobs: int, rate_per_s: float, n_lo: int = 1000,
                   n_hi: int = 256000, steps_lo: int = 1000,
                   steps_hi: int = 100000, t_lo: float = 0.45,
-                  t_hi: float = 1.0, seed: int = MASTER_SEED) -> List[Job]:
+                  t_hi: float = 1.0, seed: int = MASTER_SEED,
+                  tcf_fraction: float = 0.0, tcf_every: int = 10,
+                  tcf_levels: int = 4, tcf_block: int = 10) -> List[Job]:
     """Poisson arrivals (exponential gaps at `rate_per_s`) of KA jobs with
     N log-uniform in [n_lo, n_hi], steps uniform in [steps_lo, steps_hi],
-    T uniform in [t_lo, t_hi]."""
+    T uniform in [t_lo, t_hi]; a seeded `tcf_fraction` of them also ask for
+    time-correlation functions sampled every `tcf_every` steps (wave number
+    q = 7.25, the first peak of the KA structure factor, Sec. 5)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 5])))
     gaps = rng.exponential(1.0 / rate_per_s, size=n_jobs)
     arr = np.cumsum(gaps) - gaps[0]
@@ -222,7 +232,9 @@ def serving_trace(n_jobs: int, rate_per_s: float, n_lo: int = 1000,
     st = rng.integers(steps_lo, steps_hi + 1, size=n_jobs)
     ts = rng.uniform(t_lo, t_hi, size=n_jobs)
     seeds = rng.integers(1, 2**31 - 1, size=n_jobs)
-    return [Job(i, float(arr[i]), int(ns[i]), int(st[i]), float(ts[i]), int(seeds[i]))
+    wants = rng.uniform(size=n_jobs) < tcf_fraction
+    return [Job(i, float(arr[i]), int(ns[i]), int(st[i]), float(ts[i]), int(seeds[i]),
+                tcf_every=tcf_every if wants[i] else 0, tcf_levels=tcf_levels, tcf_block=tcf_block)
             for i in range(n_jobs)]
 
 

@@ -16,7 +16,14 @@ graph-captured steps.  Between chunks it
     still fails once nothing else is running (e.g. its first Verlet lists
     exceed the pool's capacity);
   * retires with an error result a job whose replica stopped with an error
-    bit (a list that outgrew its capacity, non-finite coordinates).
+    bit (a list that outgrew its capacity, non-finite coordinates);
+  * for a job that asks for time-correlation functions (Sec. 2.5), binds a
+    blocking scheme to its slot at admission, stops the replica at a full
+    step every tcf_every steps (its step target), samples it there, and
+    returns the MSD / VACF / F_s curves with the job's result.  Stopping
+    at a full step and resuming leaves the trajectory bitwise unchanged,
+    so the curves are the ones the job computes alone.  Each advance runs
+    up to the nearest target of any running job.
 
 A replica's trajectory does not depend on the other replicas in the pool,
 so every job's result is bitwise the one it would get alone.
@@ -45,6 +52,7 @@ class JobResult:
     vel: Optional[np.ndarray]
     image: Optional[np.ndarray]
     error: Optional[str] = None
+    tcf: Optional[dict] = None  # lags (samples), values [levels, block-1, species, (MSD, VACF, F_s)], terms
 
     @property
     def latency(self) -> float:
@@ -100,9 +108,25 @@ class Server:
                 return "wait"
             return str(e)  # refused by an empty pool: it never fits
         self.free.pop(0)
-        self.pool.set_target(slot, job.steps)
-        self.running[slot] = {"job": job, "admitted": now}
+        r = {"job": job, "admitted": now, "tcf": None}
+        every = int(getattr(job, "tcf_every", 0) or 0)
+        if every > 0:
+            r["tcf"] = self.pool.tcf(slot, job.tcf_levels, job.tcf_block, job.tcf_q)
+            r["tcf"].sample()  # the replica starts at a full step
+            r["next_sample"] = every
+        r["target"] = min(job.steps, r["next_sample"]) if r["tcf"] is not None else job.steps
+        self.pool.set_target(slot, r["target"])
+        self.running[slot] = r
         return "admitted"
+
+    def _release(self, slot):
+        r = self.running.pop(slot)
+        if r["tcf"] is not None:
+            r["tcf"].close()
+        self.pool.detach(slot)
+        self.free.append(slot)
+        self.free.sort()
+        return r
 
     def run(self, jobs: List, time_scale: float = 1.0, log: Optional[Callable] = None) -> dict:
         """Serve `jobs` (md_inputs.Job, sorted by arrival).  Arrival times are
@@ -138,35 +162,47 @@ class Server:
                     time.sleep(max(0.0, pending[pi].arrival * time_scale - (time.perf_counter() - t0)))
                 continue
             tb = time.perf_counter()
-            self.pool.advance(self.chunk)
+            # up to the nearest target of a running job (a sample point or its
+            # last step), plus the launch that finalises it at a full step
+            launches = self.chunk
+            for slot, r in self.running.items():
+                launches = min(launches, max(1, r["target"] - r.get("steps", 0) + 1))
+            self.pool.advance(launches)
             steps, status = self.pool.poll()
             busy += time.perf_counter() - tb
             now = time.perf_counter() - t0
             for slot in list(self.running):
                 r = self.running[slot]
                 job = r["job"]
+                r["steps"] = int(steps[slot])
                 if status[slot] & 0xFF:  # the replica stopped with an error bit
                     results.append(JobResult(job.job_id, self.pool.sizes[slot], job.steps,
                                              job.arrival * time_scale, r["admitted"], now, None, None,
                                              None, error=f"stopped at step {int(steps[slot])} with "
                                                          f"status bits {int(status[slot]) & 0xFF:#x}"))
-                    self.pool.detach(slot)
-                    self.free.append(slot)
-                    self.free.sort()
-                    del self.running[slot]
+                    self._release(slot)
                     if log:
                         log(f"job {job.job_id} failed: {results[-1].error}")
                     continue
+                at_target = steps[slot] >= r["target"] and status[slot] & mdx.MD_ST_AT_FULL_STEP
+                if at_target and r["tcf"] is not None and steps[slot] == r["next_sample"]:
+                    r["tcf"].sample()
+                    r["next_sample"] += job.tcf_every
+                if at_target and steps[slot] < job.steps:  # a sample point: on to the next target
+                    r["target"] = min(job.steps, r["next_sample"])
+                    self.pool.set_target(slot, r["target"])
+                    continue
                 if steps[slot] >= job.steps and status[slot] & mdx.MD_ST_AT_FULL_STEP:
                     pos, vel, img = self.pool.get_state(slot)
+                    curves = None
+                    if r["tcf"] is not None:
+                        lags, vals, terms = r["tcf"].read()
+                        curves = {"lags": lags, "values": vals, "terms": terms, "every": job.tcf_every}
                     results.append(JobResult(job.job_id, self.pool.sizes[slot], job.steps,
                                              job.arrival * time_scale, r["admitted"], now,
-                                             pos, vel, img))
+                                             pos, vel, img, tcf=curves))
                     work += self.pool.sizes[slot] * job.steps
-                    self.pool.detach(slot)
-                    self.free.append(slot)
-                    self.free.sort()
-                    del self.running[slot]
+                    self._release(slot)
                     if log:
                         log(f"job {job.job_id} n={results[-1].n} steps={job.steps} "
                             f"latency {results[-1].latency:.3f}s")

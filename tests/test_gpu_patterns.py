@@ -329,3 +329,66 @@ def test_list_overflow_mid_run_stops_the_replica_and_spares_the_others():
         ref.step(210)
         assert _same(_state(ref), mixed[k]), k
         ref.close()
+
+
+def test_served_time_correlations_equal_alone_and_follow_the_oracle():
+    """Jobs that ask for time-correlation functions (Sec. 2.5) while served
+    in a continuously batched pool: each job's curves are bitwise the ones it
+    computes alone, and a small job's curves match the oracle's blocking
+    scheme on the oracle's own trajectory."""
+    import math
+    from oracle import oracle as O
+    from oracle import tcf as OT
+    from oracle.upload import state_after_upload
+    from paper_0912_3824_amd.serve import Server
+    jobs = I.serving_trace(6, rate_per_s=60.0, n_lo=500, n_hi=4000, steps_lo=150, steps_hi=400, seed=8,
+                           tcf_fraction=1.0, tcf_every=10, tcf_levels=3, tcf_block=4)
+    jobs[1].tcf_every = 0          # a job without correlations in the mix
+    jobs[2].tcf_every = 7
+    jobs[0].n = 500                # the one the oracle follows
+    say("served tcf jobs", [(j.n, j.steps, j.tcf_every) for j in jobs])
+    srv = Server(I.ka_table(), "ds", max_slots=3, max_particles=9000, chunk_steps=64,
+                 make_system=lambda j: I.job_system(j))
+    out = srv.run(jobs)
+    srv.close()
+    res = {r.job_id: r for r in out["results"]}
+    assert not out["failed"] and len(res) == len(jobs)
+    assert res[1].tcf is None
+    for j in jobs:
+        r = res[j.job_id]
+        alone = pool_for([I.job_system(j)], "ds")
+        if j.tcf_every:
+            t = alone.tcf(0, j.tcf_levels, j.tcf_block, j.tcf_q)
+            t.sample()
+            done = 0
+            while done + j.tcf_every <= j.steps:
+                alone.step(j.tcf_every)
+                done += j.tcf_every
+                t.sample()
+            if done < j.steps:
+                alone.step(j.steps - done)
+            lags, vals, terms = t.read()
+            assert np.array_equal(lags, r.tcf["lags"]) and np.array_equal(terms, r.tcf["terms"])
+            assert np.array_equal(vals, r.tcf["values"], equal_nan=True), j
+        else:
+            alone.step(j.steps)
+        p, v, i = alone.get_state(0)
+        assert np.array_equal(p, r.pos) and np.array_equal(v, r.vel) and np.array_equal(i, r.image), j
+        alone.close()
+    # the oracle's scheme on the oracle's trajectory for the smallest job
+    j = jobs[0]
+    s = I.job_system(j)
+    p, v, img = state_after_upload(s.pos, s.vel, s.box, "ds")
+    ref = OT.Blocking(j.tcf_levels, j.tcf_block, s.species, j.tcf_q)
+    ref.sample(p + img * s.box, v)
+    for _ in range(j.steps // j.tcf_every):
+        p, v, di, _ = O.vv(p, v, s.box, s.species, s.table, s.dt, j.tcf_every)
+        img = img + di
+        ref.sample(p + img * s.box, v)
+    rl, rv, rt = ref.result()
+    got = res[j.job_id].tcf
+    assert (got["terms"] == rt).all()
+    ok = rt > 0
+    err = np.abs(got["values"][ok] - rv[ok]) / (np.abs(rv[ok]) + 1e-3)
+    say("served tcf vs oracle: max rel err", float(err.max()))
+    assert err.max() < 1e-4

@@ -94,7 +94,8 @@ def batch(n_rep=256, steps=2000, warmup=200, alone_sample=16, precision="ds", se
 
 
 def serve(n_jobs=40, load=0.8, steps_lo=1000, steps_hi=10000, n_lo=1000, n_hi=256000,
-          max_slots=32, hbm_budget_gb=4.0, chunk=256, precision="ds", seed=20240101):
+          max_slots=32, hbm_budget_gb=4.0, chunk=256, precision="ds", seed=20240101,
+          rebuild_every=0, rebuild_early=0.0, skin=0.3, shape=None, tcf_fraction=0.0):
     import md_inputs as I
     from paper_0912_3824_amd import mdx
     from paper_0912_3824_amd.serve import Server
@@ -107,23 +108,26 @@ def serve(n_jobs=40, load=0.8, steps_lo=1000, steps_hi=10000, n_lo=1000, n_hi=25
     mean_job = math.exp((math.log(n_hi) + math.log(n_lo)) / 2) * 1.15 * (steps_lo + steps_hi) / 2
     rate = load * cap / mean_job
     jobs = I.serving_trace(n_jobs, rate, n_lo=n_lo, n_hi=n_hi, steps_lo=steps_lo,
-                           steps_hi=steps_hi, seed=seed)
+                           steps_hi=steps_hi, seed=seed, tcf_fraction=tcf_fraction)
     max_particles = Server.bytes_for_budget(I.ka_table(), precision, hbm_budget_gb * 1e9, max_slots)
     log(f"serve: {n_jobs} jobs at {rate:.2f}/s (offered load {load}), arena {max_particles} particles")
-    srv = Server(I.ka_table(), precision, max_slots=max_slots, max_particles=max_particles,
-                 chunk_steps=chunk, make_system=lambda j: I.job_system(j))
+    kw = dict(rebuild_every=rebuild_every, rebuild_early=rebuild_early)
+    srv = Server(I.ka_table(), precision, max_slots=max_slots, max_particles=max_particles, skin=skin,
+                 chunk_steps=chunk, make_system=lambda j: I.job_system(j, skin=skin), shape=shape, **kw)
     out = srv.run(jobs)
     srv.close()
     # the same jobs, one after another, each alone
     work, wall = 0, 0.0
     for j in jobs:
-        s = I.job_system(j)
-        q = mdx.md_init([s], precision)
+        s = I.job_system(j, skin=skin)
+        q = mdx.md_init([s], precision, **kw)
         wall += _timed_step(q, j.steps)
         work += s.n * j.steps
         q.close()
     res = {k: v for k, v in out.items() if k != "results"}
     res.update({"jobs": n_jobs, "rate_per_s": rate, "offered_load": load, "max_slots": max_slots,
+                "rebuild_every": rebuild_every, "rebuild_early": rebuild_early, "skin": skin,
+                "tcf_jobs": sum(1 for j in jobs if j.tcf_every),
                 "arena_particles": max_particles, "chunk_steps": chunk, "precision": precision,
                 "alone_sequential_particle_steps_per_s": work / wall,
                 "served_vs_alone": res["throughput_busy"] / (work / wall),
@@ -231,6 +235,7 @@ if __name__ == "__main__":
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--alone-sample", type=int, default=16)
     ap.add_argument("--shape", default=None, help="launch shape as JSON (md_launch fields)")
+    ap.add_argument("--tcf-fraction", type=float, default=0.0, help="serve: jobs asking for correlations")
     a = ap.parse_args()
     if a.mode == "batch":
         r = batch(a.replicas, a.steps, precision=a.precision, rebuild_every=a.rebuild_every,
@@ -241,5 +246,8 @@ if __name__ == "__main__":
     elif a.mode == "thermo":
         r = thermo(steps=a.steps, precision=a.precision)
     else:
-        r = serve(a.jobs, a.load, a.steps_lo, a.steps_hi, precision=a.precision)
+        r = serve(a.jobs, a.load, a.steps_lo, a.steps_hi, precision=a.precision,
+                  rebuild_every=a.rebuild_every, rebuild_early=a.rebuild_early,
+                  skin=a.skin if a.skin is not None else 0.3,
+                  shape=json.loads(a.shape) if a.shape else None, tcf_fraction=a.tcf_fraction)
     print(json.dumps(r))

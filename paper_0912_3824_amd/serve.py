@@ -71,10 +71,15 @@ class Server:
 
     def __init__(self, table, precision="ds", dt=0.001, skin=0.3, max_slots=32,
                  max_particles=2_000_000, chunk_steps=256, device="cuda:0",
-                 make_system: Optional[Callable] = None, pool=None):
+                 make_system: Optional[Callable] = None, pool=None, shape: Optional[dict] = None,
+                 **cfg_kw):
+        """cfg_kw: further md_config fields (e.g. rebuild_every, rebuild_early);
+        shape: launch shape (md_launch fields) for the pool."""
         if pool is None:
-            cfg = mdx.make_config(table, precision, dt, skin, max_slots, max_particles)
+            cfg = mdx.make_config(table, precision, dt, skin, max_slots, max_particles, **cfg_kw)
             pool = mdx.MdSystem(cfg, device=device)
+            if shape:
+                pool.set_launch(**shape)
         self.pool = pool
         self.chunk = int(chunk_steps)
         self.max_slots = max_slots

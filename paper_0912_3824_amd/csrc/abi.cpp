@@ -615,6 +615,7 @@ static md_status run_launches(md_system *s, int64_t n)
 // Small control kernels live in aux_kernels.hip; declare the launchers here.
 hipError_t launch_add_targets(int *target, const Ctl *ctl, int max_slots, int delta, hipStream_t s);
 hipError_t launch_poke(int *p, int v, hipStream_t s);
+hipError_t launch_void_stored(Ctl *ctl, int max_slots, hipStream_t s);
 
 // ------------------------------------------------------------ host helpers
 struct HostRep {
@@ -1186,13 +1187,22 @@ md_status md_detach(md_system *s, int32_t slot)
     return upload_items(s);
 }
 
+// The observation launch writes each force as one double into the rows
+// where a finalising launch keeps its forces for the next step.  In double-
+// single those rows hold both words of each sum, which one double need not
+// represent, so the next step evaluates the forces again.
+static hipError_t void_stored_after_obs(md_system *s)
+{
+    if (s->prec != MD_DS) return hipSuccess;
+    return launch_void_stored(s->ctl[s->parity], (int)s->lay.slots, s->stream);
+}
+
 md_status md_rebuild_neighbours(md_system *s)
 {
     if (!s) return MD_E_ARG;
     const int p = s->parity, kp = p ^ 1;
     // the re-sort moves particles between slots: forces stored by slot are void
-    for (int k = 0; k < (int)s->lay.slots; ++k)
-        if (s->slots[k].attached) HIPCHK(s, launch_poke((int *)(s->ctl[p] + k) + 3, 0, s->stream));
+    HIPCHK(s, launch_void_stored(s->ctl[p], (int)s->lay.slots, s->stream));
     HIPCHK(s, hipMemsetAsync(s->count[kp], 0, 4 * s->lay.cells, s->stream));
     CountArgs ca;
     memset(&ca, 0, sizeof ca);
@@ -1214,6 +1224,7 @@ md_status md_forces(md_system *s, int32_t slot, double *f_host, double *e_host)
     if (!s) return MD_E_ARG;
     StepArgs a = step_args(s, s->parity);
     HIPCHK(s, launch_step(s->prec, a, s->launch.step_block, true, s->stream));
+    HIPCHK(s, void_stored_after_obs(s));
     if (!f_host && !e_host) return MD_OK;
     md_status st = check_slot(s, slot, true);
     if (st != MD_OK) return st;
@@ -1288,6 +1299,7 @@ md_status md_observables(md_system *s, md_obs *out)
     const int S = (int)s->lay.slots;
     StepArgs a = step_args(s, s->parity);
     HIPCHK(s, launch_step(s->prec, a, s->launch.step_block, true, s->stream));
+    HIPCHK(s, void_stored_after_obs(s));
     ObsArgs oa;
     oa.max_slots = S;
     oa.rep = s->rep;

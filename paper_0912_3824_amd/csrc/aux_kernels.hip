@@ -318,9 +318,22 @@ __global__ void k_add_targets(int *target, const Ctl *ctl, int max_slots, int de
 
 __global__ void k_poke(int *p, int v) { *p = v; }
 
+// Forget the forces a finalising launch stored (control word w) for every slot.
+__global__ void k_void_stored(Ctl *ctl, int max_slots)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < max_slots) ctl[s].w = 0;
+}
+
 hipError_t launch_add_targets(int *target, const Ctl *ctl, int max_slots, int delta, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_targets, dim3((max_slots + 255) / 256), dim3(256), 0, s, target, ctl, max_slots, delta);
+    LAUNCH_CHECK();
+}
+
+hipError_t launch_void_stored(Ctl *ctl, int max_slots, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_void_stored, dim3((max_slots + 255) / 256), dim3(256), 0, s, ctl, max_slots);
     LAUNCH_CHECK();
 }
 

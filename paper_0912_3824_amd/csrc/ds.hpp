@@ -59,6 +59,20 @@ __host__ __device__ __forceinline__ double ds_to_double(dsf a)
     return (double)a.hi + (double)a.lo;
 }
 
+// Both words of a double-single number in one 64-bit word, bit for bit (a
+// conversion to double rounds when the words' bits span more than 53 bits).
+__device__ __forceinline__ double ds_pack(dsf a)
+{
+    const unsigned long long u = ((unsigned long long)__float_as_uint(a.lo) << 32) | __float_as_uint(a.hi);
+    return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ dsf ds_unpack(double w)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(w);
+    return {__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32))};
+}
+
 __device__ __forceinline__ dsf ds_add(dsf a, dsf b)
 {
     float s, e;

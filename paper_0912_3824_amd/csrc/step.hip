@@ -468,9 +468,9 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     } else {
         FAcc<P> acc;
         DsForce F;
-        if (stored) { // the stored doubles hold each force exactly
+        if (stored) { // each stored word holds its force bit for bit
             if (sub != 0) return;
-            if constexpr (P == PREC_DS) F = {ds_from_double(ost[0]), ds_from_double(ost[1]), ds_from_double(ost[2])};
+            if constexpr (P == PREC_DS) F = {ds_unpack(ost[0]), ds_unpack(ost[1]), ds_unpack(ost[2])};
             else if constexpr (P == PREC_FP32) { acc.x = (float)ost[0]; acc.y = (float)ost[1]; acc.z = (float)ost[2]; }
             else { acc.x = ost[0]; acc.y = ost[1]; acc.z = ost[2]; }
         } else {
@@ -488,7 +488,9 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
         if (sub != 0) return;
         if (mode == M_FIN && !OBS) { // keep the forces for the next step
             double *o = a.obs + (size_t)i * 8;
-            if constexpr (P == PREC_DS) { o[0] = ds_to_double(F.x); o[1] = ds_to_double(F.y); o[2] = ds_to_double(F.z); }
+            // double-single: both words (hi + lo need not fit one double);
+            // FP32 and FP64 sums convert exactly
+            if constexpr (P == PREC_DS) { o[0] = ds_pack(F.x); o[1] = ds_pack(F.y); o[2] = ds_pack(F.z); }
             else { o[0] = acc.x; o[1] = acc.y; o[2] = acc.z; }
         }
         if (OBS) {

@@ -91,11 +91,20 @@ def test_graph_eager_shapes_and_split_calls_are_bitwise_equal():
                          (dict(graph_steps=2), [100, 100, 200]),
                          (dict(build_lanes=1, build_block=512), [400]),
                          (dict(build_lanes=64, build_block=1024, build_width=1), [200, 200]),
-                         (dict(build_lanes=4, build_block=128, build_width=3), [400])]:
+                         (dict(build_lanes=4, build_block=128, build_width=3), [400]),
+                         # observation launches between calls overwrite the
+                         # rows that hold the finalising launch's forces
+                         (dict(graph_steps=32), [150, "obs", 1, "forces", 249]),
+                         (dict(graph_steps=0), [7, "forces", "obs", 393])]:
         pool = pool_for([s], "ds")
         pool.set_launch(**shape)
         for c in calls:
-            pool.step(c)
+            if c == "obs":
+                pool.observables()
+            elif c == "forces":
+                pool.forces(0)
+            else:
+                pool.step(c)
         st = _state(pool)
         if ref is None:
             ref = st

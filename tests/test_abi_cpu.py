@@ -55,6 +55,13 @@ def test_validation_rejects_bad_configs():
         setattr(c, field, val)
         assert mdx.md_validate(c) == -1, field
         assert mdx.md_workspace_bytes(c) == -1
+    # list entries are byte offsets of 16-byte records: at most 2^28 slots
+    c = _cfg()
+    c.max_particles = (1 << 28) - 256
+    assert mdx.md_validate(c) == 0
+    c.max_particles = (1 << 28) - 255
+    assert mdx.md_validate(c) == -1
+    assert mdx.md_workspace_bytes(c) == -1
     c = _cfg()
     c.eps[1] = 2.0   # asymmetric table
     assert mdx.md_validate(c) == -1

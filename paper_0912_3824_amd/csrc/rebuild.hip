@@ -431,16 +431,53 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         return r2 < (((int)xj.w < 0) ? rl2s1 : rl2s0);
     };
     // The candidates of staged cell k in order (i itself is skipped).  Each
-    // chunk of up to 64 candidates is tested four at a time (independent
-    // reads in flight, no stores and no branches in the test loop: a wave
-    // would otherwise run the store path whenever any of its lanes accepts)
-    // into an acceptance mask, whose set bits are then stored in order.
+    // chunk of up to 64 (32 when staged) candidates is tested four at a
+    // time (independent reads in flight, no stores and no branches in the
+    // test loop: a wave would otherwise run the store path whenever any of
+    // its lanes accepts) into an acceptance mask, whose set bits are then
+    // stored in order.
+    //
+    // Staged candidates are read at fixed offsets from the chunk's start,
+    // past the cell's end too (into the next cell's records or the padding
+    // that follows the staged array): those tests are masked off once per
+    // chunk instead of clamping every read.  The list is written through a
+    // running pointer to entry cnt.
+    int *wp = col; // entry cnt: row cnt/4, lane cnt%4
+    auto put = [&](int g) {
+        if (cnt < cap) *wp = list_entry(g);
+        wp += (cnt & 3) == 3 ? (ptrdiff_t)row_stride - 3 : 1;
+        ++cnt;
+    };
     auto scan_cell = [&](int k) {
         const int4 c = T.pk[k];
         const int na = T.na[k], n = c.y;
         auto at = [&](int e) { return cand_at<FROM_LDS>(c, na, e); };
         const int self = (unsigned)(i - c.z) < (unsigned)na ? i - c.z
                        : (unsigned)(i - c.w) < (unsigned)(n - na) ? na + (i - c.w) : -1;
+        if constexpr (FROM_LDS) {
+            const uint4 *cp = cand + NS * c.x; // the cell's staged records
+            for (int base = 0; base < n; base += 32) {
+                unsigned mask = 0;
+                for (int e = 0; e < n - base; e += 4) {
+                    const uint4 *q = cp + NS * (base + e);
+                    const Cand q0 = {q[0], q[NS - 1]}, q1 = {q[NS], q[2 * NS - 1]},
+                               q2 = {q[2 * NS], q[3 * NS - 1]}, q3 = {q[3 * NS], q[4 * NS - 1]};
+                    const unsigned bits = (eval(q0) ? 1u : 0u) | (eval(q1) ? 2u : 0u) | (eval(q2) ? 4u : 0u) |
+                                          (eval(q3) ? 8u : 0u);
+                    mask |= bits << e;
+                    if (e == 28) break; // a full chunk of 32
+                }
+                const int m = n - base;
+                if (m < 32) mask &= (1u << m) - 1u;
+                if ((unsigned)(self - base) < 32u) mask &= ~(1u << (self - base));
+                while (mask) {
+                    const int b = __ffs(mask) - 1;
+                    mask &= mask - 1u;
+                    put(cand_glob(c, na, base + b));
+                }
+            }
+            return;
+        }
         for (int base = 0; base < n; base += 64) {
             const int m = min(64, n - base), last = base + m - 1;
             unsigned long long mask = 0;
@@ -459,8 +496,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             while (mask) {
                 const int b = __ffsll((long long)mask) - 1;
                 mask &= mask - 1;
-                if (cnt < cap) col[4 * ((unsigned long long)(unsigned)(cnt >> 2) * (unsigned)P_) + (cnt & 3)] = list_entry(cand_glob(c, na, base + b));
-                ++cnt;
+                put(cand_glob(c, na, base + b));
             }
         }
     };
@@ -853,9 +889,16 @@ hipError_t occupancy_permute(int prec, int *per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, 256, 0);
 }
 
+// Staged records plus four of padding: the one-lane scan reads up to three
+// records past a cell's end (masked off), also past the last staged cell.
+static size_t build_lds_bytes(int prec, int lds_cap)
+{
+    return (size_t)(lds_cap + 4) * 16 * (prec == PREC_FP64 ? 2 : 1);
+}
+
 hipError_t occupancy_build(int prec, int block, int lds_cap, int *per_cu)
 {
-    const size_t lds = (size_t)lds_cap * 16 * (prec == PREC_FP64 ? 2 : 1);
+    const size_t lds = build_lds_bytes(prec, lds_cap);
     const void *f;
     switch (prec) {
     case PREC_FP32: f = (const void *)k_build<PREC_FP32>; break;
@@ -868,7 +911,7 @@ hipError_t occupancy_build(int prec, int block, int lds_cap, int *per_cu)
 
 hipError_t launch_build(int prec, const BuildArgs &a, int grid, int block, hipStream_t s)
 {
-    size_t lds = (size_t)a.lds_cap * 16 * (prec == PREC_FP64 ? 2 : 1);
+    const size_t lds = build_lds_bytes(prec, a.lds_cap);
     switch (prec) {
     case PREC_FP32: hipLaunchKernelGGL((k_build<PREC_FP32>), dim3(grid), dim3(block), lds, s, a); break;
     case PREC_DS: hipLaunchKernelGGL((k_build<PREC_DS>), dim3(grid), dim3(block), lds, s, a); break;

@@ -13,6 +13,7 @@ Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
 import argparse
 import json
+import statistics
 import math
 import os
 import sys
@@ -55,6 +56,26 @@ WORKLOADS = {
     "lj4000": ("LJ fcc start, N=4000, rho=0.8442, T=1.5, rc=2.5, skin=0.3, dt=0.001", "fp64"),
     "batch256": ("256 KA replicas, N log-uniform [500,8000], rho=1.2, T in {0.45,0.5,0.6,0.8}", "ds"),
 }
+
+
+def energy_drift(n: int, steps: int, seed: int) -> dict:
+    """Energy drift per 1e5 steps in every precision mode: one KA replica
+    equilibrated in FP64 (velocity rescaling), then the same state run NVE
+    for `steps` steps in each mode (paper_0912_3824_amd.drift)."""
+    from paper_0912_3824_amd import drift as D
+    r = D.run(n=n, temperature=0.7, steps=steps, every=100, equil=2000, seed=seed)
+    keep = ("slope_per_1e5_steps", "stderr_per_1e5_steps", "relative_slope_per_1e5_steps",
+            "relative_stderr", "rms_dev_from_e0", "max_abs_momentum_per_particle")
+    modes = {p: {k: float(f"{v[k]:.4g}") for k in keep} for p, v in r["results"].items()}
+    ds, f64 = r["results"]["ds"], r["results"]["fp64"]
+    out = {"workload": f"Kob-Andersen N={n}, rho=1.2, T=0.7, dt=0.001, unsmoothed cutoff, {steps} NVE "
+                       "steps from one FP64-equilibrated state, E_tot/N sampled every 100 steps",
+           "unit": "eps per particle per 1e5 steps (OLS slope, block-averaged standard error)",
+           "modes": modes,
+           "ds_no_worse_than_fp64": bool(abs(ds["slope_per_1e5_steps"]) <=
+                                         abs(f64["slope_per_1e5_steps"]) + 2 * ds["stderr_per_1e5_steps"])}
+    log(f"energy drift: {out}")
+    return out
 
 
 def log(*a):
@@ -203,6 +224,9 @@ def main():
     ap.add_argument("--skin", type=float, default=None, help="Verlet skin (default: the workload's)")
     ap.add_argument("--cell-order", default="row", choices=["row", "morton", "hilbert"],
                     help="order of the cells in the particle sort")
+    ap.add_argument("--drift-steps", type=int, default=100000,
+                    help="NVE steps of the energy-drift measurement in every precision (0: skip)")
+    ap.add_argument("--drift-n", type=int, default=64000, help="particles of the drift measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -256,6 +280,10 @@ def main():
     # per-kernel timing with hipEvents on the pool's stream (eager launches)
     prof = pool.profile_steps(args.profile_steps)
     log(f"profile: {prof}")
+    # The fused kernel without its force loop: the first launch of a call
+    # reuses the forces the previous call's finalising launch stored, so it
+    # runs only the integration, snapshot, displacement test and cell count.
+    integ_ms = statistics.median(pool.profile_steps(1)["step_kernel_ms"] for _ in range(21))
     # force-only kernel (md_forces: force, energy, virial; no integration)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 20
@@ -299,6 +327,8 @@ def main():
     roof["valu_issue_utilisation"] = round(ops_launch / (k_ms * 1e-3) / 1e12 / VALU_ISSUE_PEAK_TOPS, 4)
     log(f"roofline: {roof}")
 
+    drift = energy_drift(args.drift_n, args.drift_steps, args.seed) if args.drift_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         big = systems[0] if len(systems) == 1 else max(systems, key=lambda q: q.n)
@@ -330,9 +360,11 @@ def main():
                       "rebuild_group_ms_mean": round(prof["rebuild_ms_mean"], 5),
                       "rebuild_group_ms_when_rebuilding": round(prof["rebuild_ms_when_rebuilding"], 5),
                       "eager_ms_per_step": round(prof["total_ms"] / args.profile_steps, 5),
-                      "force_only_kernel_ms": round(force_ms, 5)},
+                      "force_only_kernel_ms": round(force_ms, 5),
+                      "integrator_only_kernel_ms": round(integ_ms, 5)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "energy_drift": drift,
     }
     print(json.dumps(out), flush=True)
     if args.calib_copy:  # a copy of known size: 256 MiB read + 256 MiB written

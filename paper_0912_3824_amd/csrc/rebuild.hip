@@ -540,8 +540,7 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
 template <int P, bool FROM_LDS>
 __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDev &rp, int i, int lx_m,
                                                  const BuildTabs &T, bool full, const uint4 *cand, int s,
-                                                 int nd, int G, int gl, unsigned long long gmask,
-                                                 unsigned long long below)
+                                                 int nd, int G, int gl, unsigned long long gmask)
 {
     constexpr int NS = Traits<P>::NS;
     const KArena &A = a.A;
@@ -593,25 +592,35 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
     // one cell's candidates (in the one-lane build's order), 4G at a time:
     // lane gl tests e = b + u G + gl (u = 0..3, independent loads in
     // flight); the ballots are taken in u order, which is ascending e
+    // (the member's own candidate index is excluded by position, its global
+    // slot is formed only for the entries stored, and the store address is
+    // one 32 x 32 -> 64-bit multiply-add: row_stride < 2^32 since P < 2^28)
     int cnt = 0;
+    const unsigned rs32 = (unsigned)row_stride;
     auto scan_cell = [&](int k) {
         const int4 c = T.pk[k];
         const int na = T.na[k], n = c.y;
+        const int self = (unsigned)(i - c.z) < (unsigned)na ? i - c.z
+                       : (unsigned)(i - c.w) < (unsigned)(n - na) ? na + (i - c.w) : -1;
         for (int b = 0; b < n; b += 4 * G) {
             bool acc[4];
-            int g[4];
+            int ev[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) { // past the end: test the last candidate, masked off
                 const int e = b + u * G + gl, ec = min(e, n - 1);
-                g[u] = cand_glob(c, na, ec);
-                acc[u] = test(cand_at<FROM_LDS>(c, na, ec)) && e < n && g[u] != i;
+                ev[u] = e;
+                acc[u] = test(cand_at<FROM_LDS>(c, na, ec)) && e < n && e != self;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const unsigned long long m = __ballot(acc[u]) & gmask;
-                if (acc[u]) {
-                    const int k2 = cnt + __popcll(m & below);
-                    if (k2 < cap) col[(size_t)(k2 >> 2) * row_stride + (k2 & 3)] = list_entry(g[u]);
+                if (acc[u]) { // rank among the group's accepting lanes below this one
+                    const unsigned k2 = (unsigned)cnt +
+                        __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    if (k2 < (unsigned)cap) {
+                        const size_t idx = (size_t)(k2 >> 2) * rs32 + (k2 & 3u);
+                        col[idx] = list_entry(cand_glob(c, na, ev[u]));
+                    }
                 }
                 cnt += __popcll(m);
             }
@@ -832,12 +841,11 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             const int lane = t & 63, gl = t & (G - 1);
             const unsigned long long gmask =
                 G == 64 ? ~0ull : ((1ull << G) - 1ull) << (lane & ~(G - 1));
-            const unsigned long long below = (1ull << lane) - 1ull;
             for (int k = m0 + t / G; k < m1; k += B / G) {
                 int i, lx_m;
                 member(k, i, lx_m);
-                if (fits) build_member_grp<P, true>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
-                else build_member_grp<P, false>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask, below);
+                if (fits) build_member_grp<P, true>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask);
+                else build_member_grp<P, false>(a, rp, i, lx_m, T, full, cand, s, nd, G, gl, gmask);
                 if (gl == 0) copy_back<P>(a, i);
             }
         }

@@ -1730,13 +1730,14 @@ md_status md_debug_neighbours(md_system *s, int32_t slot, int32_t *counts, int32
     if (st != MD_OK) return st;
     if (!counts || !ids || cap < 1) return fail(s, MD_E_ARG, "null output");
     const SlotHost &h = s->slots[slot];
-    const int64_t n = h.n, P = s->lay.P, lc = s->lay.cap;
-    std::vector<int> cnt(n), lst((size_t)n * lc);
+    const int64_t n = h.n, lc = s->lay.cap;
+    // the list tiles that hold the replica's slots: one contiguous range
+    const int64_t t0 = h.off / LIST_TILE, t1 = (h.off + n + LIST_TILE - 1) / LIST_TILE;
+    const size_t row0 = list_row_index((int)(t0 * LIST_TILE), 0, (int)lc);
+    std::vector<int> cnt(n), lst((size_t)(t1 - t0) * LIST_TILE * lc);
     std::vector<int4> mt(n);
     HIPCHK(s, hipMemcpyAsync(cnt.data(), s->nbr_cnt + h.off, 4 * n, hipMemcpyDeviceToHost, s->stream));
-    // blocked layout: entry k of slot i at int4 row k/4, lane k%4
-    HIPCHK(s, hipMemcpy2DAsync(lst.data(), 16 * n, s->nbr + 4 * h.off, 16 * P, 16 * n, lc / 4,
-                               hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(lst.data(), s->nbr + 4 * row0, 4 * lst.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipMemcpyAsync(mt.data(), s->meta + h.off, 16 * n, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     for (int64_t k = 0; k < n; ++k) {
@@ -1746,7 +1747,8 @@ md_status md_debug_neighbours(md_system *s, int32_t slot, int32_t *counts, int32
         for (int q = 0; q < cap; ++q) {
             int v = -1;
             if (q < cnt[k] && q < lc) {
-                int j = list_slot(lst[(size_t)(q >> 2) * 4 * n + 4 * k + (q & 3)]) - (int)h.off;
+                const size_t r = list_row_index((int)(h.off + k), q >> 2, (int)lc) - row0;
+                int j = list_slot(lst[4 * r + (q & 3)]) - (int)h.off;
                 v = (j >= 0 && j < n) ? mt[j].w : -2;
             }
             ids[(size_t)id * cap + q] = v;

@@ -7,9 +7,11 @@
 //   snapshot      : uint4 snap[2][NS][P]  ping-pong, read by neighbours
 //   reference pos : uint4 xref[NS][P]     positions at the last list build
 //   meta          : int4 meta[P]          (image x, image y, image z, id)
-//   list count    : int nbr_cnt[P];  list: int nbr[cap][P] (column-major;
-//                   an entry is the neighbour's slot times 16, the byte
-//                   offset of its 16-byte snapshot record)
+//   list count    : int nbr_cnt[P];  list: int4 rows in tiles of 64 slots
+//                   (row q of slot i at list_row_index(i, q, cap); the rows
+//                   of a tile are contiguous, and row q of its 64 slots is
+//                   1 KB contiguous); an entry is the neighbour's slot times
+//                   16, the byte offset of its 16-byte snapshot record
 //   observation   : double obs[P][8]      (fx, fy, fz, e_i, w_i, vx, vy, vz)
 // plus a scratch copy of st/snap/meta used by the cell sort.
 //
@@ -125,6 +127,15 @@ __host__ __device__ __forceinline__ double bits_of_meta(uint32_t m)
 // List entry of slot j: the byte offset of its snapshot record.
 __host__ __device__ __forceinline__ int list_entry(int j) { return (int)((uint32_t)j << 4); }
 __host__ __device__ __forceinline__ int list_slot(int e) { return (int)((uint32_t)e >> 4); }
+
+// int4 row q (entries 4q..4q+3) of the list of slot i: tiles of LIST_TILE
+// slots, each holding its cap/4 rows one after another.  P is a multiple of
+// the tile, so the P * cap / 4 rows fill the list array exactly.
+#define LIST_TILE 64
+__host__ __device__ __forceinline__ size_t list_row_index(int i, int q, int cap)
+{
+    return ((size_t)(i / LIST_TILE) * (size_t)(cap >> 2) + (size_t)q) * LIST_TILE + (size_t)(i % LIST_TILE);
+}
 #define NO_SLOT 0xFFFFFFFFu
 
 // Species (0 = A, 1 = B) of a meta word.

@@ -394,9 +394,9 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         rl2s1 = (float)(rl2d1 / (u * u));
     }
     const int cap = A.cap;
-    // entry k of slot i: int4 row k/4, lane k%4 (see list_row)
-    int *col = A.nbr_w + 4 * (size_t)i;
-    const size_t row_stride = 4 * P_;
+    // entry k of slot i: int4 row k/4, lane k%4 (see list_row_index)
+    int *col = A.nbr_w + 4 * list_row_index(i, 0, cap);
+    const size_t row_stride = 4 * LIST_TILE;
     int cnt = 0;
     // a candidate's snapshot (two words for double snapshots) at staged
     // index x (a global slot when nothing is staged), then the test
@@ -563,8 +563,8 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
         rl2s1 = (float)(rl2d1 / (u * u));
     }
     const int cap = A.cap;
-    int *col = A.nbr_w + 4 * (size_t)i;
-    const size_t row_stride = 4 * P_;
+    int *col = A.nbr_w + 4 * list_row_index(i, 0, cap);
+    const size_t row_stride = 4 * LIST_TILE;
     // test the candidate at staged index x (a global slot when nothing is staged)
     auto test = [&](int x) -> bool {
         if (NS == 2) {
@@ -594,7 +594,7 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
     // flight); the ballots are taken in u order, which is ascending e
     // (the member's own candidate index is excluded by position, its global
     // slot is formed only for the entries stored, and the store address is
-    // one 32 x 32 -> 64-bit multiply-add: row_stride < 2^32 since P < 2^28)
+    // one 32 x 32 -> 64-bit multiply-add)
     int cnt = 0;
     const unsigned rs32 = (unsigned)row_stride;
     auto scan_cell = [&](int k) {

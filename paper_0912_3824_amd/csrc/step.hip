@@ -153,12 +153,13 @@ __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, con
 enum { PK_GENERAL = 0, PK_UNIFORM = 1, PK_SMOOTH = 2 };
 
 // The Verlet list of particle i is stored in blocks of four entries:
-// entry k lives in int4 row k/4, lane k%4, of column i (nbr4[(k/4)*P + i]),
-// so one dwordx4 load fetches four indices and a wave reads 1 KB contiguous.
+// entry k lives in int4 row k/4, lane k%4 (rows in tiles of 64 slots, see
+// list_row_index), so one dwordx4 load fetches four indices and the lanes
+// of a wave read 512 B runs.
 typedef int v4i __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int4 list_row(const KArena &A, int i, int q)
 {
-    const v4i *p = (const v4i *)A.nbr + (size_t)q * A.P + i;
+    const v4i *p = (const v4i *)A.nbr + list_row_index(i, q, A.cap);
     v4i v = __builtin_nontemporal_load(p); // streamed once per step: keep it out of the caches
     return make_int4(v.x, v.y, v.z, v.w);
 }

@@ -24,7 +24,8 @@ sys.path.insert(0, ROOT)
 
 # MI355X vendor peaks.  VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
 # x 2.4 GHz = 78.6 TFLOP/s for FP32 (and FP64) without packed-FP32 dual
-# issue, which this build does not use; the 157.3 TFLOP/s headline needs it.
+# issue, which the library's kernels are compiled without; the 157.3 TFLOP/s
+# headline needs it.
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12          # 78.6
 VALU_PACKED_PEAK_TFLOPS = 2 * VALU_PEAK_TFLOPS              # 157.3
@@ -233,7 +234,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding of this "
-              "path is a design note, not part of this build", file=sys.stderr)
+              "path is not implemented: the library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -153,15 +153,15 @@ class Server:
             while queue:
                 job, sys_ = queue[0]
                 now = time.perf_counter() - t0
-                verdict = self._try_admit(job, sys_, now)
-                if verdict == "wait":
+                outcome = self._try_admit(job, sys_, now)
+                if outcome == "wait":
                     break
                 queue.pop(0)
-                if verdict != "admitted":
+                if outcome != "admitted":
                     results.append(JobResult(job.job_id, sys_.n, job.steps, job.arrival * time_scale,
-                                             now, now, None, None, None, error=verdict))
+                                             now, now, None, None, None, error=outcome))
                     if log:
-                        log(f"job {job.job_id} n={sys_.n} rejected: {verdict}")
+                        log(f"job {job.job_id} n={sys_.n} rejected: {outcome}")
             if not self.running:
                 if pi < len(pending):  # idle until the next arrival
                     time.sleep(max(0.0, pending[pi].arrival * time_scale - (time.perf_counter() - t0)))

@@ -270,7 +270,15 @@ md_status md_forces(md_system *sys, int32_t slot, double *f_host, double *e_host
  * next step, drift, displacement check) plus the rebuild kernels, which do
  * work only for replicas whose maximum displacement since their last build
  * exceeds skin/2.  Replays captured hipGraphs where possible.  Replicas end
- * at full-step velocities.  Asynchronous. */
+ * at full-step velocities.  Asynchronous.
+ *
+ * The launch that brings a replica to its full step keeps its forces, and the
+ * next call's first launch uses them instead of evaluating forces again at
+ * the same positions, so n calls of one step cost as many force passes as one
+ * call of n steps, with bitwise the same trajectory.  md_rebuild_neighbours,
+ * md_thermostat and, in double-single mode, md_forces and md_observables
+ * (which overwrite the rows that hold them) drop the kept forces; the next
+ * call then evaluates them. */
 md_status md_step(md_system *sys, int64_t n_steps);
 
 /* Serving form: set the absolute step at which a replica stops

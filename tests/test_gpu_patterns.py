@@ -340,6 +340,43 @@ def test_list_overflow_mid_run_stops_the_replica_and_spares_the_others():
         ref.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "ds"])
+def test_overlapping_particles_stop_the_replica_and_spare_the_others(prec):
+    """Two particles placed 1e-4 sigma apart: their first pair force
+    overflows FP32, their positions become non-finite, and the replica stops
+    with MD_ST_NONFINITE in its status; md_poll and md_observables report
+    MD_E_NONFINITE, launching calls refuse until it is detached, and the
+    other replica of the pool is bitwise what it is alone."""
+    from paper_0912_3824_amd import mdx
+    normal = I.make_ka(1500, 0.6, jitter=0.05, seed=52)
+    bad = I.make_ka(1500, 0.6, jitter=0.05, seed=53)
+    pos = bad.pos.copy()
+    pos[0] = pos[1] + np.array([1e-4, 0.0, 0.0])
+    bad.pos = pos
+    pool = pool_for([normal, bad], prec)
+    pool.step(20)
+    steps, status = pool.poll()
+    say("non-finite run:", prec, "steps", steps[:2].tolist(), "status", status[:2].tolist())
+    assert status[1] & mdx.MD_ST_NONFINITE
+    assert steps[1] < 20 and steps[0] == 20
+    assert not (status[0] & 0xFF)
+    with pytest.raises(mdx.MdError) as ei:
+        pool.observables()
+    assert ei.value.status == mdx.MD_E_NONFINITE
+    with pytest.raises(mdx.MdError) as ei:
+        pool.step(1)
+    assert ei.value.status == mdx.MD_E_NONFINITE
+    pool.detach(1)
+    pool.step(5)
+    mixed = _state(pool, 0)
+    assert pool.observables()[0]["status"] == 0
+    pool.close()
+    ref = pool_for([normal], prec)
+    ref.step(25)
+    assert _same(_state(ref), mixed)
+    ref.close()
+
+
 def test_served_time_correlations_equal_alone_and_follow_the_oracle():
     """Jobs that ask for time-correlation functions (Sec. 2.5) while served
     in a continuously batched pool: each job's curves are bitwise the ones it

@@ -112,6 +112,27 @@ def test_graph_eager_shapes_and_split_calls_are_bitwise_equal():
         pool.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed64", "fp64"])
+def test_observation_between_calls_is_bitwise_in_every_mode(prec):
+    """The forces a call's finalising launch keeps are reused by the next
+    call; md_forces and md_observables in between (which write the same rows)
+    leave the trajectory bitwise unchanged in the other precision modes too."""
+    s = I.make_ka(4001, 0.7, jitter=0.05, seed=8)
+    runs = []
+    for calls in ([400], [150, "obs", 1, "forces", 249], [7, "forces", "obs", 393]):
+        pool = pool_for([s], prec)
+        for c in calls:
+            if c == "obs":
+                pool.observables()
+            elif c == "forces":
+                pool.forces(0)
+            else:
+                pool.step(c)
+        runs.append(_state(pool))
+        pool.close()
+    assert _same(runs[0], runs[1]) and _same(runs[0], runs[2])
+
+
 @pytest.mark.parametrize("prec", ["ds", "mixed64", "fp64"])
 def test_checkpoint_resume_is_bitwise(prec):
     s = I.make_ka(3001, 0.7, jitter=0.08, seed=9)

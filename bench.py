@@ -79,6 +79,12 @@ def energy_drift(n: int, steps: int, seed: int) -> dict:
     return out
 
 
+# Lanes per particle of the fused kernel's force sum (a pool setting; it fixes
+# the summation order).  Two by default; four for the 4000-particle system,
+# whose 4000 particles would otherwise fill only 125 waves.
+LANES_PER_PARTICLE = {"lj4000": 4}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -248,7 +254,8 @@ def main():
     n_total = sum(s.n for s in systems)
     log(f"workload {args.workload}: {len(systems)} replica(s), {n_total} particles, precision {prec}")
 
-    pool = mdx.md_init(systems, prec, skin=args.skin, cell_order=args.cell_order)
+    lpp = LANES_PER_PARTICLE.get(args.workload, 0)
+    pool = mdx.md_init(systems, prec, skin=args.skin, cell_order=args.cell_order, lanes_per_particle=lpp)
     from paper_0912_3824_amd import tune
     tuned = tune.apply_cached(pool)  # launch shapes from the autotuner, if tuned
     pool.set_launch(graph_steps=args.graph_steps)
@@ -363,7 +370,7 @@ def main():
                    "cell_order": args.cell_order,
                    "graph_steps": args.graph_steps, "equil_steps": args.equil,
                    "graph_priming_steps": prime,
-                   "launch": pool.get_launch(),
+                   "launch": pool.get_launch(), "lanes_per_particle": lpp or 2,
                    "mean_list_entries": round(mean_list, 3), "rebuilds_in_timed_region": int(rebuilds)},
         "breakdown": {"step_kernel_ms": round(k_ms, 5),
                       "rebuild_group_ms_mean": round(prof["rebuild_ms_mean"], 5),

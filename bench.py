@@ -85,6 +85,30 @@ def energy_drift(n: int, steps: int, seed: int) -> dict:
 LANES_PER_PARTICLE = {"lj4000": 4}
 
 
+def pattern_rates(single_rate: float) -> dict:
+    """The batching and serving patterns beside the single system: 256 KA
+    replicas advanced together (aligned rebuilds) against a sample of them
+    advanced one at a time, and 40 served jobs at offered load 0.9 against
+    the same jobs run one after another (paper_0912_3824_amd.patterns_bench)."""
+    from paper_0912_3824_amd import patterns_bench as PB
+    b = PB.batch(256, 1000, alone_sample=8, rebuild_every=16, rebuild_early=0.6, skin=0.4)
+    v = PB.serve(40, 0.9)
+    out = {"unit": "particle-steps/s",
+           "single_system": single_rate,
+           "batch256": {"replicas": b["replicas"], "particles": b["particles"], "steps": b["steps"],
+                        "settings": "aligned rebuilds every 16 steps past 0.6 of skin/2, skin 0.4",
+                        "batched": b["batched_particle_steps_per_s"], "us_per_step": b["batched_us_per_step"],
+                        "alone_sample": b["alone_sample"], "alone": b["alone_particle_steps_per_s"],
+                        "speedup_vs_alone": b["speedup_vs_alone"]},
+           "serve": {"jobs": v["jobs"], "offered_load": v["offered_load"],
+                     "p50_latency_s": v["p50_latency_s"], "p99_latency_s": v["p99_latency_s"],
+                     "served_busy": v["throughput_busy"], "served_wall": v["throughput_wall"],
+                     "alone_sequential": v["alone_sequential_particle_steps_per_s"],
+                     "served_vs_alone": v["served_vs_alone"], "failed": v["failed"]}}
+    log(f"patterns: {out}")
+    return out
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -234,6 +258,8 @@ def main():
     ap.add_argument("--drift-steps", type=int, default=100000,
                     help="NVE steps of the energy-drift measurement in every precision (0: skip)")
     ap.add_argument("--drift-n", type=int, default=64000, help="particles of the drift measurement")
+    ap.add_argument("--no-patterns", action="store_true",
+                    help="skip the batched (256 replicas) and served (40 jobs) pattern measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -343,6 +369,7 @@ def main():
     log(f"roofline: {roof}")
 
     drift = energy_drift(args.drift_n, args.drift_steps, args.seed) if args.drift_steps > 0 else None
+    patterns = None if args.no_patterns or args.workload != "ka1m" else pattern_rates(value)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -381,6 +408,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "energy_drift": drift,
+        "patterns": patterns,
     }
     print(json.dumps(out), flush=True)
     if args.calib_copy:  # a copy of known size: 256 MiB read + 256 MiB written

@@ -355,6 +355,9 @@ def main():
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm_frac, 4)}
     roof["traffic"] = read_traffic(args.workload, prec, n_total, args.cell_order)
+    if roof["traffic"]:  # the counters' bytes (MALL hits included) over the same time: not the roofline
+        roof["measured_traffic_gbs"] = round(roof["traffic"] / (k_ms * 1e-3) / 1e9, 1)
+        roof["measured_traffic_frac"] = round(roof["measured_traffic_gbs"] / HBM_PEAK_GBS, 4)
     roof["kernel"] = f"k_step<{prec}> (fused force + velocity Verlet)"
     roof["kernel_ms"] = round(k_ms, 5)
     roof["algorithmic_bytes_per_launch"] = int(bytes_launch)

@@ -201,10 +201,11 @@ static Layout layout_of(const md_config *c)
     L.P = align_up(c->max_particles, 256);
     double rho = c->max_density > 0 ? c->max_density : 1.2;
     double rl = rlist_max_of(c);
-    if (c->nbr_capacity > 0) L.cap = align_up(c->nbr_capacity, 8);
+    // a multiple of 16: lists are padded to four entries per lane of a particle
+    if (c->nbr_capacity > 0) L.cap = align_up(c->nbr_capacity, 16);
     else {
         double mean = 4.18879020478639 * rl * rl * rl * rho; // (4/3) pi r^3 rho
-        L.cap = align_up((int64_t)std::ceil(1.3 * mean + 16.0), 8);
+        L.cap = align_up((int64_t)std::ceil(1.3 * mean + 16.0), 16);
     }
     L.slots = c->max_slots;
     L.cells = (c->max_cells > 0 ? c->max_cells : c->max_particles / 2 + 64) + c->max_slots;
@@ -421,6 +422,7 @@ static KArena arena_of(const md_system *s)
     KArena A;
     A.P = (int)s->lay.P;
     A.cap = (int)s->lay.cap;
+    A.lg = s->lpp == 4 ? 2 : s->lpp == 2 ? 1 : 0;
     for (int k = 0; k < 3; ++k) A.st[k] = s->st[k];
     A.xref = s->xref;
     A.xref_w = s->xref;
@@ -1747,8 +1749,9 @@ md_status md_debug_neighbours(md_system *s, int32_t slot, int32_t *counts, int32
         for (int q = 0; q < cap; ++q) {
             int v = -1;
             if (q < cnt[k] && q < lc) {
-                const size_t r = list_row_index((int)(h.off + k), q >> 2, (int)lc) - row0;
-                int j = list_slot(lst[4 * r + (q & 3)]) - (int)h.off;
+                const int lg = s->lpp == 4 ? 2 : s->lpp == 2 ? 1 : 0;
+                const size_t r = list_row_index((int)(h.off + k), list_entry_row(q, lg), (int)lc) - row0;
+                int j = list_slot(lst[4 * r + list_entry_col(q, lg)]) - (int)h.off;
                 v = (j >= 0 && j < n) ? mt[j].w : -2;
             }
             ids[(size_t)id * cap + q] = v;

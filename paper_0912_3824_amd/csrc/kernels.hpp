@@ -6,7 +6,8 @@
 
 struct KArena {
     int P;            // arena stride (particle slots)
-    int cap;          // neighbour-list capacity per particle
+    int cap;          // neighbour-list capacity per particle (a multiple of 16)
+    int lg;           // log2 of the lanes per particle that read a list (entry layout)
     uint4 *st[3];     // state words
     const uint4 *xref;
     uint4 *xref_w;    // same memory as xref

@@ -128,13 +128,30 @@ __host__ __device__ __forceinline__ double bits_of_meta(uint32_t m)
 __host__ __device__ __forceinline__ int list_entry(int j) { return (int)((uint32_t)j << 4); }
 __host__ __device__ __forceinline__ int list_slot(int e) { return (int)((uint32_t)e >> 4); }
 
-// int4 row q (entries 4q..4q+3) of the list of slot i: tiles of LIST_TILE
-// slots, each holding its cap/4 rows one after another.  P is a multiple of
-// the tile, so the P * cap / 4 rows fill the list array exactly.
+// int4 row q of the list of slot i: tiles of LIST_TILE slots, each holding
+// its cap/4 rows one after another.  P is a multiple of the tile, so the
+// P * cap / 4 rows fill the list array exactly.
 #define LIST_TILE 64
 __host__ __device__ __forceinline__ size_t list_row_index(int i, int q, int cap)
 {
     return ((size_t)(i / LIST_TILE) * (size_t)(cap >> 2) + (size_t)q) * LIST_TILE + (size_t)(i % LIST_TILE);
+}
+
+// The L lanes of a particle (L = 1, 2 or 4, lg = log2 L) read its list in
+// rows of four entries, lane l taking rows l, l + L, l + 2L, ...  Entries
+// are dealt to the lanes in turn, so that the lanes of a particle gather
+// neighbouring entries (often one cache line) in the same instruction:
+// entry k sits in row L (k / 4L) + k % L, column (k / L) % 4.  A list is
+// padded to a multiple of 4L entries (the capacity is a multiple of 16) and
+// fills L ceil(n / 4L) rows.
+__host__ __device__ __forceinline__ int list_entry_row(int k, int lg)
+{
+    return ((k >> (lg + 2)) << lg) | (k & ((1 << lg) - 1));
+}
+__host__ __device__ __forceinline__ int list_entry_col(int k, int lg) { return (k >> lg) & 3; }
+__host__ __device__ __forceinline__ int list_rows(int n, int lg)
+{
+    return ((n + (4 << lg) - 1) >> (lg + 2)) << lg;
 }
 #define NO_SLOT 0xFFFFFFFFu
 

@@ -394,9 +394,10 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
         rl2s1 = (float)(rl2d1 / (u * u));
     }
     const int cap = A.cap;
-    // entry k of slot i: int4 row k/4, lane k%4 (see list_row_index)
+    // entry k of slot i: int4 row list_entry_row(k), column list_entry_col(k)
     int *col = A.nbr_w + 4 * list_row_index(i, 0, cap);
     const size_t row_stride = 4 * LIST_TILE;
+    const int lg = A.lg, lm = (1 << lg) - 1, gm = (4 << lg) - 1;
     int cnt = 0;
     // a candidate's snapshot (two words for double snapshots) at staged
     // index x (a global slot when nothing is staged), then the test
@@ -442,11 +443,13 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
     // that follows the staged array): those tests are masked off once per
     // chunk instead of clamping every read.  The list is written through a
     // running pointer to entry cnt.
-    int *wp = col; // entry cnt: row cnt/4, lane cnt%4
+    int *wp = col; // entry cnt (see list_entry_row): the next lane's row, else
+                   // the next column of the first lane's row, else the next group
     auto put = [&](int g) {
         if (cnt < cap) *wp = list_entry(g);
-        wp += (cnt & 3) == 3 ? (ptrdiff_t)row_stride - 3 : 1;
         ++cnt;
+        wp += (cnt & lm) ? (ptrdiff_t)row_stride : (cnt & gm) ? 1 - (ptrdiff_t)lm * (ptrdiff_t)row_stride
+                                                                : (ptrdiff_t)row_stride - 3;
     };
     auto scan_cell = [&](int k) {
         const int4 c = T.pk[k];
@@ -506,13 +509,14 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
 #pragma unroll 1
     for (int v = 0; v < nvis; ++v) scan_cell(nd == 1 ? 0 : visit_cell(v, lx_m, full, nd, NX));
     const int last_cell = nd == 1 ? 0 : visit_cell(26, lx_m, full, nd, NX);
-    // Pad the list to a multiple of 4 with a particle that is outside the
+    // Pad the list to a multiple of 4 entries per lane of a particle
+    // (list_entry_row) with a particle that is outside the
     // list radius at this build: it stays beyond the force cutoff until the
     // next build (each particle moves at most skin/2), so the force loop
     // needs no per-entry validity test.  The pad is the first rejected
     // candidate of the last cell visited (a corner cell), else of any
     // staged cell.
-    if (cnt & 3) {
+    if (cnt & gm) {
         int pad = -1;
         for (int k = 0, kk = last_cell; k <= T.ncell && pad < 0; kk = k++) {
             const int4 c = T.pk[kk];
@@ -523,8 +527,8 @@ __device__ __forceinline__ void build_member(const BuildArgs &a, const RepDev &r
             }
         }
         if (pad < 0) atomicOr(a.status + s, 8);
-        for (int k = cnt; k < ((cnt + 3) & ~3) && k < cap; ++k)
-            col[(size_t)(k >> 2) * row_stride + (k & 3)] = list_entry(pad < 0 ? i : pad);
+        for (int k = cnt; k < ((cnt + gm) & ~gm) && k < cap; ++k)
+            col[(size_t)list_entry_row(k, lg) * row_stride + list_entry_col(k, lg)] = list_entry(pad < 0 ? i : pad);
     }
     A.nbr_cnt_w[i] = cnt < A.cap ? cnt : A.cap;
     if (cnt > A.cap) atomicOr(a.status + s, 1);
@@ -565,6 +569,7 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
     const int cap = A.cap;
     int *col = A.nbr_w + 4 * list_row_index(i, 0, cap);
     const size_t row_stride = 4 * LIST_TILE;
+    const int lg = A.lg, gm = (4 << lg) - 1;
     // test the candidate at staged index x (a global slot when nothing is staged)
     auto test = [&](int x) -> bool {
         if (NS == 2) {
@@ -618,7 +623,8 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
                     const unsigned k2 = (unsigned)cnt +
                         __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                     if (k2 < (unsigned)cap) {
-                        const size_t idx = (size_t)(k2 >> 2) * rs32 + (k2 & 3u);
+                        const size_t idx = (size_t)(unsigned)list_entry_row((int)k2, lg) * rs32 +
+                                           (unsigned)list_entry_col((int)k2, lg);
                         col[idx] = list_entry(cand_glob(c, na, ev[u]));
                     }
                 }
@@ -631,9 +637,10 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
 #pragma unroll 1
     for (int v = 0; v < nvis; ++v) scan_cell(nd == 1 ? 0 : visit_cell(v, lx_m, full, nd, NX));
     const int last_cell = nd == 1 ? 0 : visit_cell(26, lx_m, full, nd, NX);
-    // pad to a multiple of 4, as in the one-lane build: the first rejected
-    // candidate of the last visited cell, else (rare) of any staged cell
-    if (cnt & 3) {
+    // pad to a multiple of 4 entries per lane of a particle, as in the
+    // one-lane build: the first rejected candidate of the last visited
+    // cell, else (rare) of any staged cell
+    if (cnt & gm) {
         int pad = -1;
         {
             const int4 cl = T.pk[last_cell];
@@ -656,8 +663,9 @@ __device__ __forceinline__ void build_member_grp(const BuildArgs &a, const RepDe
                 }
             }
             if (pad < 0) atomicOr(a.status + s, 8);
-            for (int k = cnt; k < ((cnt + 3) & ~3) && k < cap; ++k)
-                col[(size_t)(k >> 2) * row_stride + (k & 3)] = list_entry(pad < 0 ? i : pad);
+            for (int k = cnt; k < ((cnt + gm) & ~gm) && k < cap; ++k)
+                col[(size_t)list_entry_row(k, lg) * row_stride + list_entry_col(k, lg)] =
+                    list_entry(pad < 0 ? i : pad);
         }
     }
     if (gl == 0) {

@@ -226,11 +226,12 @@ __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int e)
 }
 
 // Force (and optionally energy/virial) on particle i from its list.  Lists
-// are padded to a multiple of four entries; lane `sub` of the particle's
-// `lpp` lanes takes blocks sub, sub + lpp, sub + 2 lpp, ... of four entries,
-// two of them per iteration of a software-pipelined loop (while one block
-// is computed, the snapshots of the next and the indices of the one after
-// it are in flight), and an odd last block after it.  Row indices are
+// are padded to four entries per lane and their entries dealt to the lanes
+// in turn (list_entry_row): lane `sub` of the particle's `lpp` lanes takes
+// rows sub, sub + lpp, sub + 2 lpp, ... of four entries (every lane the same
+// number), two of them per iteration of a software-pipelined loop (while one
+// block is computed, the snapshots of the next and the indices of the one
+// after it are in flight), and an odd last block after it.  Row indices are
 // clamped, so every prefetch is unconditional and no control-flow join
 // forces the memory counters to drain inside the loop.
 template <int P, bool EN, int KIND>
@@ -239,7 +240,7 @@ __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__rest
                                             FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp)
 {
     const int cnt = A.nbr_cnt[i];
-    const int nq = (cnt + 3) >> 2; // blocks of four (a partial block is completed by padding)
+    const int nq = list_rows(cnt, A.lg); // rows of four (a partial group is completed by padding)
     acc.init();
     if (sub >= nq) return;
     const int last = nq - 1;
@@ -298,7 +299,7 @@ __device__ __forceinline__ void force_dbl(const KArena &A, const uint4 *__restri
     rc2[0] = pp.rc2d[si * 2]; rc2[1] = pp.rc2d[si * 2 + 1];
     sig2[0] = pp.sig2d[si * 2]; sig2[1] = pp.sig2d[si * 2 + 1];
     e24[0] = pp.eps24d[si * 2]; e24[1] = pp.eps24d[si * 2 + 1];
-    const int nq = (cnt + 3) >> 2; // blocks of four (a partial block is completed by padding)
+    const int nq = list_rows(cnt, A.lg); // rows of four (a partial group is completed by padding)
     for (int q = sub; q < nq; q += lpp) {
         const int4 jj = list_row(A, i, q);
         const int js[4] = {jj.x, jj.y, jj.z, jj.w};

@@ -59,19 +59,25 @@ WORKLOADS = {
 }
 
 
-def energy_drift(n: int, steps: int, seed: int) -> dict:
-    """Energy drift per 1e5 steps in every precision mode: one KA replica
-    equilibrated in FP64 (velocity rescaling), then the same state run NVE
-    for `steps` steps in each mode (paper_0912_3824_amd.drift)."""
+def energy_drift(n: int, steps: int, seed: int, replicas: int) -> dict:
+    """Energy drift per 1e5 steps in every precision mode: `replicas`
+    independent KA replicas equilibrated in FP64 (velocity rescaling), then
+    the same states run NVE for `steps` steps in each mode, all replicas in
+    one pool (paper_0912_3824_amd.drift).  A mode's drift is the replicas'
+    mean slope; its standard error is their spread over sqrt(replicas)."""
     from paper_0912_3824_amd import drift as D
-    r = D.run(n=n, temperature=0.7, steps=steps, every=100, equil=2000, seed=seed)
+    r = D.run(n=n, temperature=0.7, steps=steps, every=100, equil=2000, seed=seed, replicas=replicas)
     keep = ("slope_per_1e5_steps", "stderr_per_1e5_steps", "relative_slope_per_1e5_steps",
-            "relative_stderr", "rms_dev_from_e0", "max_abs_momentum_per_particle")
+            "relative_stderr", "mean_block_stderr_per_1e5_steps", "rms_dev_from_e0",
+            "max_abs_momentum_per_particle")
     modes = {p: {k: float(f"{v[k]:.4g}") for k in keep} for p, v in r["results"].items()}
+    for p, v in r["results"].items():
+        modes[p]["replica_slopes_per_1e5_steps"] = [float(f"{x:.3g}") for x in v["replica_slopes_per_1e5_steps"]]
     ds, f64 = r["results"]["ds"], r["results"]["fp64"]
-    out = {"workload": f"Kob-Andersen N={n}, rho=1.2, T=0.7, dt=0.001, unsmoothed cutoff, {steps} NVE "
-                       "steps from one FP64-equilibrated state, E_tot/N sampled every 100 steps",
-           "unit": "eps per particle per 1e5 steps (OLS slope, block-averaged standard error)",
+    out = {"workload": f"{replicas} Kob-Andersen replicas of N={n}, rho=1.2, T=0.7, dt=0.001, unsmoothed cutoff, "
+                       f"{steps} NVE steps from FP64-equilibrated states, E_tot/N sampled every 100 steps",
+           "unit": "eps per particle per 1e5 steps (mean OLS slope over the replicas; standard error from "
+                   "their spread)",
            "modes": modes,
            "ds_no_worse_than_fp64": bool(abs(ds["slope_per_1e5_steps"]) <=
                                          abs(f64["slope_per_1e5_steps"]) + 2 * ds["stderr_per_1e5_steps"])}
@@ -257,7 +263,8 @@ def main():
                     help="order of the cells in the particle sort")
     ap.add_argument("--drift-steps", type=int, default=100000,
                     help="NVE steps of the energy-drift measurement in every precision (0: skip)")
-    ap.add_argument("--drift-n", type=int, default=64000, help="particles of the drift measurement")
+    ap.add_argument("--drift-n", type=int, default=64000, help="particles of a replica of the drift measurement")
+    ap.add_argument("--drift-replicas", type=int, default=8, help="independent replicas of the drift measurement")
     ap.add_argument("--no-patterns", action="store_true",
                     help="skip the batched (256 replicas) and served (40 jobs) pattern measurements")
     ap.add_argument("--calib-copy", action="store_true",
@@ -371,7 +378,8 @@ def main():
     roof["valu_issue_utilisation"] = round(ops_launch / (k_ms * 1e-3) / 1e12 / VALU_ISSUE_PEAK_TOPS, 4)
     log(f"roofline: {roof}")
 
-    drift = energy_drift(args.drift_n, args.drift_steps, args.seed) if args.drift_steps > 0 else None
+    drift = (energy_drift(args.drift_n, args.drift_steps, args.seed, args.drift_replicas)
+             if args.drift_steps > 0 else None)
     patterns = None if args.no_patterns or args.workload != "ka1m" else pattern_rates(value)
 
     cpu = None

@@ -116,6 +116,28 @@ def test_list_build_lanes_give_identical_lists(prec, n):
     pool.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+def test_lists_do_not_depend_on_lanes_per_particle(prec):
+    """The entries of a list are dealt to the lanes of its particle in turn,
+    so where an entry is stored depends on the lanes per particle (1, 2 or
+    4); read back in the canonical order, the lists are the same entry by
+    entry for every lane count, from the one-lane and the grouped-lane
+    build."""
+    s = _ka(3001)
+    ref = None
+    for lpp in (1, 2, 4):
+        pool = pool_for([s], prec, lanes_per_particle=lpp)
+        for lanes in (1, 8):
+            pool.set_launch(build_lanes=lanes)
+            pool.rebuild_neighbours()
+            cnt, ids = pool.neighbours(0, cap=256)
+            say("lists", prec, "lanes per particle", lpp, "build lanes", lanes, "entries", int(cnt.sum()))
+            if ref is None:
+                ref = (cnt, ids)
+            assert np.array_equal(cnt, ref[0]) and np.array_equal(ids, ref[1]), (lpp, lanes)
+        pool.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "ds", "mixed64"])
 def test_list_build_with_large_cells(prec):
     """Cells of ~88 members (skin 1.5, list radius 4.0): more members per

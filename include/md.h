@@ -116,7 +116,8 @@ typedef struct {
     double mass;           /* equal masses (Sec. 5); > 0 */
     double dt;             /* time step; > 0 */
     double skin;           /* Verlet skin; > 0 */
-    int32_t nbr_capacity;  /* list entries per particle; 0 = derive from max_density */
+    int32_t nbr_capacity;  /* list entries per particle, rounded up to a multiple of 16;
+                              0 = derive from max_density */
     int32_t max_slots;     /* replicas attachable at once; >= 1 */
     int64_t max_particles; /* particle arena capacity: 1 .. 2^28 - 256 (Verlet-list
                               entries are 32-bit byte offsets of 16-byte records) */

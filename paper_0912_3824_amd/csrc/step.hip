@@ -152,10 +152,10 @@ __device__ __forceinline__ LaneConsts lane_consts(const PairDev &pp, int si, con
 // pair (the test needs no per-pair cutoff), and the C2-smoothed potential.
 enum { PK_GENERAL = 0, PK_UNIFORM = 1, PK_SMOOTH = 2 };
 
-// The Verlet list of particle i is stored in blocks of four entries:
-// entry k lives in int4 row k/4, lane k%4 (rows in tiles of 64 slots, see
-// list_row_index), so one dwordx4 load fetches four indices and the lanes
-// of a wave read 512 B runs.
+// The Verlet list of particle i is stored in int4 rows of four entries
+// (rows in tiles of 64 slots, see list_row_index; which entry sits in which
+// row, see list_entry_row), so one dwordx4 load fetches four indices and the
+// lanes of a wave read 512 B runs.
 typedef int v4i __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int4 list_row(const KArena &A, int i, int q)
 {

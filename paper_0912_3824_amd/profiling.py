@@ -24,13 +24,44 @@ from collections import defaultdict
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources the fused step kernel is compiled from: counter
-    summaries taken on other sources are stale."""
+def _code_only(text: str) -> str:
+    """C++ source without its comments, whitespace runs collapsed: the part
+    of a source that the compiler sees (string and character literals kept)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_source_hash(read=None) -> str:
+    """Hash of the code (comments and layout left out) of the sources the
+    fused step kernel is compiled from: counter summaries taken on other
+    code are stale.  `read(name)` returns a source's text (default: the
+    files under csrc/)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+                return fh.read()
     h = hashlib.sha256()
     for f in ("step.hip", "dev_common.hpp", "md_dev.hpp", "ds.hpp", "kernels.hpp"):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        h.update(_code_only(read(f)).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

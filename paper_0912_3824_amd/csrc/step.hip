@@ -225,6 +225,23 @@ __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int e)
     return *(const uint4 *)((const char *)snap + (uint32_t)e);
 }
 
+// The list's row count and the first two rows of lane `sub` (the rows
+// force_fixed starts with), read before anything else is known of the slot:
+// the count and row indices are clamped to the slot's own rows, so the reads
+// stay in bounds for every slot of the arena, used or not, and the rows are
+// in flight while the replica's control words are read.
+struct ListHead { int nq; int4 r0, r1; };
+__device__ __forceinline__ ListHead list_head(const KArena &A, int i, int sub, int lpp)
+{
+    ListHead h;
+    const int cnt = min(max(A.nbr_cnt[i], 0), A.cap);
+    h.nq = list_rows(cnt, A.lg); // rows of four (a partial group is completed by padding)
+    const int last = max(h.nq - 1, 0);
+    h.r0 = list_row(A, i, min(sub, last));
+    h.r1 = list_row(A, i, min(sub + lpp, last));
+    return h;
+}
+
 // Force (and optionally energy/virial) on particle i from its list.  Lists
 // are padded to four entries per lane and their entries dealt to the lanes
 // in turn (list_entry_row): lane `sub` of the particle's `lpp` lanes takes
@@ -237,17 +254,17 @@ __device__ __forceinline__ uint4 ld_snap(const uint4 *__restrict__ snap, int e)
 template <int P, bool EN, int KIND>
 __device__ __forceinline__ void force_fixed(const KArena &A, const uint4 *__restrict__ snap, int i,
                                             uint4 xi, const LaneConsts &c, const PairDev &pp, int si,
-                                            FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp)
+                                            FAcc<P> &acc, double &e_sum, double &w_sum, int sub, int lpp,
+                                            const ListHead &h)
 {
-    const int cnt = A.nbr_cnt[i];
-    const int nq = list_rows(cnt, A.lg); // rows of four (a partial group is completed by padding)
+    const int nq = h.nq;
     acc.init();
     if (sub >= nq) return;
     const int last = nq - 1;
     const int nb = (nq - sub + lpp - 1) / lpp; // this lane's blocks
     auto row = [&](int k) { return list_row(A, i, min(sub + k * lpp, last)); };
     // block k's snapshots in a, indices of block k+1 in jb and of k+2 in ja
-    int4 ja = row(0), jb = row(1);
+    int4 ja = h.r0, jb = h.r1;
     uint4 a0 = ld_snap(snap, ja.x), a1 = ld_snap(snap, ja.y), a2 = ld_snap(snap, ja.z), a3 = ld_snap(snap, ja.w);
     ja = row(2);
     int k = 0;
@@ -368,6 +385,13 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     }
     if (i >= A.P) return;
 
+    // reads that depend on the slot alone, issued before the replica's
+    // control words are known (in bounds for every slot of the arena)
+    State<P> st;
+    st.load(A, i);
+    ListHead lh;
+    if constexpr (P != PREC_FP64) lh = list_head(A, i, sub, LPP);
+
     uint4 s0 = a.snap_cur[i];
     uint4 s1;
     uint32_t meta;
@@ -419,8 +443,6 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
     const bool stored = !OBS && mode == M_ADV && ctl.y && ctl.w;
     const double *ost = a.obs + (size_t)i * 8;
 
-    State<P> st;
-    st.load(A, i);
     // With a curve cell order, read the rank of the particle's current cell
     // now, off the critical path: a particle usually stays in its cell, and
     // the table is read again at the end only when the cell changed.
@@ -477,7 +499,7 @@ __global__ void __launch_bounds__(1024) k_step(const StepArgs a)
             else { acc.x = ost[0]; acc.y = ost[1]; acc.z = ost[2]; }
         } else {
             const LaneConsts c = lane_consts(a.pp, si, rp);
-            force_fixed<P, OBS, KIND>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum, sub, LPP);
+            force_fixed<P, OBS, KIND>(A, a.snap_cur, i, s0, c, a.pp, si, acc, e_sum, w_sum, sub, LPP, lh);
             // combine the lanes' partial sums (a no-op for one lane per particle)
             if constexpr (P == PREC_DS) F = {acc.x.result(), acc.y.result(), acc.z.result()};
 #pragma unroll

@@ -21,8 +21,8 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.jso
 
 SPACE = {
     "step_block": [256, 512, 1024],
-    "build_width": [4, 8],
-    "build_block": [256, 512],
+    "build_width": [4, 8, 10],
+    "build_block": [256, 320, 512],
     "build_lanes": [0, 16],
     "graph_steps": [32],
     "xcd_remap": [0, 1],

@@ -105,7 +105,8 @@ def test_list_build_lanes_give_identical_lists(prec, n):
     ref = None
     for lanes, block, width, split in [(1, 256, 4, 0), (2, 256, 4, 0), (4, 512, 1, 0), (8, 1024, 2, 0),
                                        (16, 256, 8, 0), (32, 64, 4, 0), (64, 1024, 4, 0), (0, 512, 8, 0),
-                                       (0, 64, 1, 0), (0, 512, 8, 1), (16, 512, 4, 3), (0, 256, 2, 256)]:
+                                       (0, 64, 1, 0), (0, 512, 8, 1), (16, 512, 4, 3), (0, 256, 2, 256), (0, 320, 10, 0),
+                                       (2, 320, 16, 0)]:
         pool.set_launch(build_lanes=lanes, build_block=block, build_width=width, build_split=split)
         pool.rebuild_neighbours()
         cnt, ids = pool.neighbours(0, cap=256)

@@ -35,8 +35,18 @@ def bucket(n_total: int) -> int:
 
 
 def key_of(pool) -> str:
+    """Cache key: precision, particle-count bucket and replicas, plus the
+    aligned-rebuild period when the pool sets one (aligned rebuilds make
+    most replicas rebuild in the same steps, which favours other
+    list-build shapes)."""
     n = sum(pool.sizes.values())
-    return f"p{pool.cfg.precision}_b{bucket(n)}_r{len(pool.sizes)}"
+    k = f"p{pool.cfg.precision}_b{bucket(n)}_r{len(pool.sizes)}"
+    every = int(getattr(pool.cfg, "rebuild_every", 0) or 0)
+    return f"{k}_a{every}" if every > 0 else k
+
+
+def _base_key(key: str) -> str:
+    return key.split("_a")[0]
 
 
 def _time_steps(pool, steps: int) -> float:
@@ -97,14 +107,16 @@ def tune(pool, steps: int = 200, space: Optional[Dict[str, List[int]]] = None,
 
 
 def apply_cached(pool, cache: str = CACHE) -> Optional[dict]:
-    """Apply a cached shape for this pool's key, if one exists."""
+    """Apply a cached shape for this pool's key (for a pool with aligned
+    rebuilds, else the key without the period), if one exists."""
     if not os.path.exists(cache):
         return None
     try:
         data = json.load(open(cache))
     except (OSError, ValueError):
         return None
-    hit = data.get(key_of(pool))
+    key = key_of(pool)
+    hit = data.get(key) or data.get(_base_key(key))  # an aligned pool falls back to the plain key
     if hit:
         pool.set_launch(**hit["shape"])
         return hit["shape"]

@@ -19,9 +19,9 @@ from gpu_helpers import TOL_F, cutoff_jump, pool_for, say
 pytestmark = pytest.mark.gpu
 
 
-def _tuned_pool(systems, prec):
+def _tuned_pool(systems, prec, **kw):
     from paper_0912_3824_amd import tune
-    pool = pool_for(systems, prec)
+    pool = pool_for(systems, prec, **kw)
     shape = tune.apply_cached(pool)
     say("launch", pool.get_launch(), "(cached)" if shape else "(defaults)")
     return pool
@@ -192,4 +192,54 @@ def test_batch256_sampled_forces_and_lists():
     pool.step(100)
     obs = pool.observables()
     assert not any(o["status"] for o in obs if o["n"])
+    pool.close()
+
+
+@pytest.mark.parametrize("aligned", [False, True])
+def test_batch256_every_particle_against_the_cell_list_oracle(aligned):
+    """Every particle of every replica of the 256-replica ensemble (716k
+    particles, double-single), in the tuned launch shapes of the pool with
+    and without aligned rebuilds: forces at the uploaded state against the
+    oracle's cell-list forces (particles with a pair within rounding of a
+    cutoff held to one cutoff jump per such pair), then ten steps against
+    its velocity Verlet over Verlet lists, max |dr| and max |dv| over all
+    particles."""
+    reps = I.make_ka_ensemble(256, seed=20240101, jitter=0.08)
+    kw = dict(rebuild_every=16, rebuild_early=0.6) if aligned else {}
+    pool = _tuned_pool(reps, "ds", **kw)
+    starts, worst_rel, worst_ef, n_over = [], 0.0, 0.0, 0
+    for k, s in enumerate(reps):
+        pos, vel, img = state_after_upload(s.pos, s.vel, s.box, "ds")
+        starts.append((pos, vel, img))
+        f, _ = pool.forces(k)
+        fr, _, _ = O.forces_cells(pos, s.box, s.species, s.table)
+        frms = math.sqrt(float(np.mean(fr * fr)))
+        rel = np.linalg.norm(f - fr, axis=1) / np.maximum(np.linalg.norm(fr, axis=1), frms)
+        d = np.abs(f - fr)
+        over = np.nonzero(rel >= TOL_F["ds"])[0]
+        keep = np.ones(s.n, dtype=bool)
+        keep[over] = False
+        if len(over):
+            near = _band_mask(pos, s.box, s.species, s.table, over, lambda a, b: s.table.rcut[a, b], 2e-6)
+            assert near.all(), k
+            assert float(d[over].max()) < 2 * cutoff_jump(s.table) + TOL_F["ds"] * frms, k
+        n_over += len(over)
+        worst_rel = max(worst_rel, float(rel[keep].max()))
+        worst_ef = max(worst_ef, float(d[keep].max()) / frms)
+    say("  forces, all replicas: per-particle relative error", worst_rel, "e_F", worst_ef,
+        "particles over the bound", n_over)
+    assert worst_ef < TOL_F["ds"]
+    assert n_over < 1e-3 * sum(s.n for s in reps)
+    pool.step(10)
+    obs = pool.observables()
+    worst_dr = worst_dv = 0.0
+    for k, s in enumerate(reps):
+        assert obs[k]["status"] == 0, k
+        p1, v1, i1 = pool.get_state(k)
+        pos, vel, img = starts[k]
+        pr, vr, ir, _, _ = O.vv_lists(pos, vel, s.box, s.species, s.table, s.dt, 10, s.skin)
+        worst_dr = max(worst_dr, float(np.abs((p1 + i1 * s.box) - (pr + (ir + img) * s.box)).max()))
+        worst_dv = max(worst_dv, float(np.abs(v1 - vr).max()))
+    say("  10 steps, all replicas: max|dr|", worst_dr, "max|dv|", worst_dv)
+    assert worst_dr <= 1e-4 and worst_dv <= 1e-4
     pool.close()

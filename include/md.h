@@ -190,7 +190,12 @@ typedef struct {
                             * members of a small replica's segments are shared out): 0 =
                             * automatic (up to 256 / segments per replica), 1 = no split,
                             * up to 256 */
-    int32_t reserved;
+    int32_t build_bulk;    /* a step's list build in which at least this many replicas rebuild
+                            * uses one lane per member and unsplit row segments for every
+                            * replica of more than one cell, whatever build_lanes and
+                            * build_split say (the shape that suits many simultaneous
+                            * rebuilds, as aligned rebuilds make); 0 = never.  Changes no
+                            * list entry. */
 } md_launch;
 
 /* ---- sizing and lifetime ------------------------------------------------ */

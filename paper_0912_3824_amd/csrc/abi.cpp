@@ -387,6 +387,15 @@ static int items4_of(const md_system *s, int n, int nd)
     return nd * nd * nseg * parts;
 }
 
+// Work items of a bulk list build (one per row segment; a single-cell
+// replica keeps its usual items).
+static int bulk_items_of(const md_system *s, int n, int nd)
+{
+    if (nd == 1) return items4_of(s, n, nd);
+    const int W = s->launch.build_width;
+    return nd * nd * (nd <= W + 2 ? 1 : (nd + W - 1) / W);
+}
+
 static md_status upload_items(md_system *s)
 {
     int S = (int)s->lay.slots;
@@ -510,6 +519,7 @@ static md_status launch_rebuild(md_system *s, int p, int force_slot, bool from_s
     ba.width = s->launch.build_width;
     ba.lds_cap = lds_cap_of(prec);
     ba.single_members = single_members(s);
+    ba.bulk = s->launch.build_bulk;
     ba.xcd = s->launch.xcd_remap;
     ba.items_pref = s->items4;
     ba.rep = s->rep;
@@ -753,6 +763,7 @@ static RepDev repdev_of(const md_system *s, const SlotHost &h)
     }
     r.items3 = h.nd * h.nd * h.nd; // a sort work item covers a cell in every plane
     r.items4 = items4_of(s, h.n, h.nd);
+    r.items4b = bulk_items_of(s, h.n, h.nd);
     build_shape(s, h.n, h.nd, r.bparts, r.blanes);
     return r;
 }
@@ -1033,7 +1044,7 @@ md_status md_create(const md_config *cfg, void *workspace, int64_t ws_bytes, voi
     s->launch.xcd_remap = 0;
     s->launch.build_lanes = 0;
     s->launch.build_split = 0;
-    s->launch.reserved = 0;
+    s->launch.build_bulk = 0;
     make_tables(s);
     {
         int dev = 0;
@@ -1779,6 +1790,7 @@ md_status md_set_launch(md_system *s, const md_launch *in)
     if (l.graph_steps != 0 && (l.graph_steps < 2 || l.graph_steps > 256 || l.graph_steps % 2))
         return fail(s, MD_E_ARG, "bad graph_steps");
     if (l.build_split < 0 || l.build_split > 256) return fail(s, MD_E_ARG, "bad build_split");
+    if (l.build_bulk < 0) return fail(s, MD_E_ARG, "bad build_bulk");
     drop_graphs(s);
     const md_launch prev = s->launch;
     s->launch = l;

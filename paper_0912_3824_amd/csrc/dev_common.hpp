@@ -83,8 +83,9 @@ __device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *
 // Work-item walk of the rebuild kernels.  A step's rebuild (force_slot -1)
 // visits the items of the slots on the rebuild list written by k_step; a
 // host-forced rebuild visits those of the selected slots (items_pref holds
-// the host's per-slot item counts as a prefix).  `unit` is this worker's
-// index among `nunits` workers; visit(slot, item) is called for each item
+// the host's per-slot item counts as a prefix).  `which` names the item
+// count of a listed slot: 3 the sort's, 4 the list build's, 5 the bulk list
+// build's.  `unit` is this worker's index among `nunits` workers; visit(slot, item) is called for each item
 // assigned to it.  Consecutive slots start on different workers so that
 // small replicas spread over the grid.  The slots and their item counts are
 // read 64 at a time, one per lane (a few round trips to memory however many
@@ -105,7 +106,7 @@ __device__ __forceinline__ void for_items(const int *rlist, const int *items_pre
         if (li < cnt) {
             if (listed) {
                 sl = rlist[1 + li];
-                its = which == 3 ? rep[sl].items3 : rep[sl].items4;
+                its = which == 3 ? rep[sl].items3 : which == 4 ? rep[sl].items4 : rep[sl].items4b;
             } else {
                 sl = li;
                 if (slot_selected(sl, force_slot, nullptr, ctl)) its = items_pref[sl + 1] - items_pref[sl];

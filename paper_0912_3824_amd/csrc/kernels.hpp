@@ -79,6 +79,7 @@ struct BuildArgs {
     KArena A;
     int max_slots, force_slot, from_scratch, width, lds_cap, xcd;
     int single_members; // members per work item of a single-cell replica
+    int bulk;           // rebuilding replicas from which a step's build is a bulk build; 0 = never
     const int *items_pref;
     const RepDev *rep;
     const int *need;

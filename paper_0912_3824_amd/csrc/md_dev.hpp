@@ -58,6 +58,7 @@ struct RepDev {
     float rc2s[4], sig2s[4], e24s[4], rcs[4], xsc[4], ihs[4];
     float hs2s;
     float hs2s_early; // (rebuild_early * skin/2)^2 / u^2 (aligned rebuilds)
+    int items4b;      // list-build work items of a bulk build (unsplit segments)
 };
 
 // Control word of a slot: x = completed steps, y = 1 if velocities are at a

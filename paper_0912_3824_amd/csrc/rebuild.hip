@@ -700,9 +700,13 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
     __shared__ BuildTabs T;
     extern __shared__ uint4 cand[];
     const int B = blockDim.x, t = threadIdx.x;
-    for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, 4,
+    // a bulk build (many replicas rebuilding together) gives each member of a
+    // multi-cell replica one lane and each row segment one work item
+    const bool bulk = a.bulk > 0 && a.force_slot == -1 && a.rlist[0] >= a.bulk;
+    for_items(a.rlist, a.items_pref, a.rep, a.max_slots, a.force_slot, a.ctl, bulk ? 5 : 4,
               remap_block(blockIdx.x, gridDim.x, a.xcd), gridDim.x, [&](int s, int item) {
         const RepDev rp = a.rep[s];
+        const int bparts = bulk ? 1 : rp.bparts;
         const int nd = rp.nd, planes = rp.planes, nc = nd * nd * nd;
         const int *cs = a.cs_new + rp.coff;
         int NX = 1, part = 0;
@@ -725,8 +729,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             const int W = a.width;
             full = nd <= W + 2;
             const int nseg = full ? 1 : (nd + W - 1) / W;
-            part = item % rp.bparts;
-            const int segitem = item / rp.bparts;
+            part = item % bparts;
+            const int segitem = item / bparts;
             const int seg = segitem % nseg, row = segitem / nseg;
             const int cy = row % nd, cz = row / nd;
             const int x0 = full ? 0 : (seg * nd) / nseg; // balanced segments
@@ -814,8 +818,8 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
             m0 = item * a.single_members;
             m1 = min(m0 + a.single_members, rp.n);
         } else {
-            m0 = (int)(((long long)part * ms) / rp.bparts);
-            m1 = (int)(((long long)(part + 1) * ms) / rp.bparts);
+            m0 = (int)(((long long)part * ms) / bparts);
+            m1 = (int)(((long long)(part + 1) * ms) / bparts);
         }
         // member index k -> slot i and the member's own-row staged cell lx
         auto member = [&](int k, int &i, int &lx) {
@@ -832,7 +836,7 @@ __global__ void __launch_bounds__(1024) k_build(const BuildArgs a)
         // lanes per member: the replica's (fixed by the launch, or one lane
         // for large replicas), else the largest power of two that still
         // gives every member of this work item its own group
-        int G = rp.blanes;
+        int G = bulk && nd > 1 ? 1 : rp.blanes;
         if (G == 0) {
             G = 1;
             while (G < 64 && (2 * G) * (m1 - m0) <= B) G *= 2;

@@ -82,12 +82,12 @@ class MdLaunch(ctypes.Structure):
     _fields_ = [("step_block", ctypes.c_int32), ("build_width", ctypes.c_int32),
                 ("build_block", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("build_lanes", ctypes.c_int32),
-                ("build_split", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("build_split", ctypes.c_int32), ("build_bulk", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k in
                 ("step_block", "build_width", "build_block", "graph_steps", "xcd_remap", "build_lanes",
-                 "build_split")}
+                 "build_split", "build_bulk")}
 
 
 class MdError(RuntimeError):

@@ -2,7 +2,8 @@
 
 The knobs (md_launch: block size of the fused step kernel, cells per LDS row
 segment, block size, lanes per member and segment split of the list build,
-steps per captured hipGraph, XCD-aware tile mapping) change no result bit: lists are in a canonical order and
+the rebuilding-replica count from which a build takes the bulk shape, steps
+per captured hipGraph, XCD-aware tile mapping) change no result bit: lists are in a canonical order and
 every particle sums its own list sequentially.  The tuner therefore times
 candidate shapes on the live pool, from a saved checkpoint so that every
 candidate advances the same trajectory, and keeps the fastest.  Results are
@@ -29,6 +30,10 @@ SPACE = {
     "build_split": [0, 4],
 }
 
+# Pools with aligned rebuilds also try the bulk build (one lane per member
+# and unsplit row segments in the steps where many replicas rebuild).
+ALIGNED_SPACE = {"build_bulk": [0, 32]}
+
 
 def bucket(n_total: int) -> int:
     return int(round(math.log2(max(n_total, 1)) * 2))
@@ -43,6 +48,13 @@ def key_of(pool) -> str:
     k = f"p{pool.cfg.precision}_b{bucket(n)}_r{len(pool.sizes)}"
     every = int(getattr(pool.cfg, "rebuild_every", 0) or 0)
     return f"{k}_a{every}" if every > 0 else k
+
+
+def space_for(pool) -> Dict[str, List[int]]:
+    """The shapes tried for a pool: SPACE, and the bulk-build threshold too
+    when the pool has aligned rebuilds."""
+    aligned = int(getattr(pool.cfg, "rebuild_every", 0) or 0) > 0
+    return dict(SPACE, **ALIGNED_SPACE) if aligned else dict(SPACE)
 
 
 def _base_key(key: str) -> str:
@@ -66,7 +78,7 @@ def tune(pool, steps: int = 200, space: Optional[Dict[str, List[int]]] = None,
     Each candidate starts from the same checkpoint of every attached slot, so
     the timed steps (including their list rebuilds) are identical work.
     """
-    space = space or SPACE
+    space = space or space_for(pool)
     slots = sorted(pool.sizes)
     blobs = {s: pool.save(s) for s in slots}
     sizes = dict(pool.sizes)

@@ -53,6 +53,32 @@ def test_batched_replicas_equal_alone(prec, align):
         alone.close()
 
 
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+def test_bulk_list_build_keeps_trajectories_bitwise(prec):
+    """A step's list build takes one lane per member and unsplit row segments
+    when at least build_bulk replicas rebuild in it.  With aligned rebuilds
+    (most replicas rebuilding in the same steps, a few early) the
+    trajectories of every replica, the single-cell one included, are the
+    same bit for bit whether no build, every build or only the crowded ones
+    take that shape."""
+    reps = _reps() + [I.make_ka(n, 0.6, jitter=0.05, seed=200 + k) for k, n in enumerate([2000, 4001, 900, 7000])]
+    ref = None
+    for shape in [dict(build_lanes=8, build_split=4, build_block=512, build_bulk=0),
+                  dict(build_lanes=8, build_split=4, build_block=512, build_bulk=1),
+                  dict(build_lanes=0, build_split=0, build_block=320, build_bulk=4),
+                  dict(build_lanes=2, build_split=2, build_block=256, build_bulk=6)]:
+        say("bulk build", prec, shape)
+        pool = pool_for(reps, prec, rebuild_every=8, rebuild_early=0.6)
+        pool.set_launch(**shape)
+        pool.step(300)
+        st = [_state(pool, k) for k in range(len(reps))]
+        assert all(o["n_rebuilds"] >= 2 for o in pool.observables()[:len(reps)])
+        pool.close()
+        if ref is None:
+            ref = st
+        assert all(_same(a, b) for a, b in zip(st, ref)), shape
+
+
 def test_aligned_rebuilds_happen_at_multiples_and_follow_the_oracle():
     """With rebuild_every = 8 the rebuilds of a replica (counted per step)
     fall on multiples of 8 unless the skin/2 rule forces one earlier, and the

@@ -35,3 +35,11 @@ def test_aligned_pool_prefers_its_own_entry_and_falls_back(tmp_path):
     assert aligned.applied == {"build_block": 320}
     assert tune.apply_cached(plain, str(cache)) == {"build_block": 512}
     assert tune.apply_cached(FakePool([10]), str(cache)) is None
+
+
+def test_aligned_pools_also_try_the_bulk_build():
+    plain = tune.space_for(FakePool([3000, 4000]))
+    aligned = tune.space_for(FakePool([3000, 4000], rebuild_every=16))
+    assert "build_bulk" not in plain
+    assert 0 in aligned["build_bulk"] and max(aligned["build_bulk"]) > 0
+    assert {k: v for k, v in aligned.items() if k != "build_bulk"} == plain

@@ -97,12 +97,14 @@ def pattern_rates(single_rate: float) -> dict:
     advanced one at a time, and 40 served jobs at offered load 0.9 against
     the same jobs run one after another (paper_0912_3824_amd.patterns_bench)."""
     from paper_0912_3824_amd import patterns_bench as PB
-    b = PB.batch(256, 1000, alone_sample=8, rebuild_every=16, rebuild_early=0.6, skin=0.4)
+    pol = PB.BATCH_POLICY
+    b = PB.batch(256, 1000, alone_sample=8, **pol)
     v = PB.serve(40, 0.9)
     out = {"unit": "particle-steps/s",
            "single_system": single_rate,
            "batch256": {"replicas": b["replicas"], "particles": b["particles"], "steps": b["steps"],
-                        "settings": "aligned rebuilds every 16 steps past 0.6 of skin/2, skin 0.4",
+                        "settings": f"aligned rebuilds every {pol['rebuild_every']} steps past "
+                                    f"{pol['rebuild_early']:g} of skin/2, skin {pol['skin']:g}",
                         "batched": b["batched_particle_steps_per_s"], "us_per_step": b["batched_us_per_step"],
                         "alone_sample": b["alone_sample"], "alone": b["alone_particle_steps_per_s"],
                         "speedup_vs_alone": b["speedup_vs_alone"]},

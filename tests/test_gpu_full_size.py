@@ -199,13 +199,15 @@ def test_batch256_sampled_forces_and_lists():
 def test_batch256_every_particle_against_the_cell_list_oracle(aligned):
     """Every particle of every replica of the 256-replica ensemble (716k
     particles, double-single), in the tuned launch shapes of the pool with
-    and without aligned rebuilds: forces at the uploaded state against the
+    and without aligned rebuilds (with: the rebuild policy and skin of the
+    ensemble measurement): forces at the uploaded state against the
     oracle's cell-list forces (particles with a pair within rounding of a
     cutoff held to one cutoff jump per such pair), then ten steps against
     its velocity Verlet over Verlet lists, max |dr| and max |dv| over all
     particles."""
     reps = I.make_ka_ensemble(256, seed=20240101, jitter=0.08)
-    kw = dict(rebuild_every=16, rebuild_early=0.6) if aligned else {}
+    from paper_0912_3824_amd import patterns_bench as PB
+    kw = dict(PB.BATCH_POLICY) if aligned else {}
     pool = _tuned_pool(reps, "ds", **kw)
     starts, worst_rel, worst_ef, n_over = [], 0.0, 0.0, 0
     for k, s in enumerate(reps):

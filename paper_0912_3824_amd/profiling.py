@@ -85,19 +85,31 @@ def kernel_stats(d):
     return "\n".join(out)
 
 
-def _counters(d):
-    acc = defaultdict(lambda: defaultdict(list))
+def _counters(d, where=None):
+    """Mean inputs per (kernel, grid): counter -> list of per-dispatch values
+    (a counter's rows of one dispatch are summed).  `where` = (counter,
+    minimum) keeps only the dispatches whose value of that counter reaches
+    the minimum (e.g. the launches of a kernel that did work)."""
+    per = defaultdict(lambda: defaultdict(float))
+    keys = {}
     for f in _find(d, "counter_collection.csv"):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                key = (r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0))
-                acc[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                did = (f, r.get("Dispatch_Id", ""))
+                keys[did] = (r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0))
+                per[did][r["Counter_Name"]] += float(r["Counter_Value"])
+    acc = defaultdict(lambda: defaultdict(list))
+    for did, cs in per.items():
+        if where and cs.get(where[0], float("-inf")) < where[1]:
+            continue
+        for c, v in cs.items():
+            acc[keys[did]][c].append(v)
     return acc
 
 
-def pmc(d):
+def pmc(d, where=None):
     out = ["kernel | grid | counter | dispatches | mean per dispatch"]
-    for (k, g), cs in sorted(_counters(d).items()):
+    for (k, g), cs in sorted(_counters(d, where).items()):
         for c, v in sorted(cs.items()):
             out.append(f"{k} | {g} | {c} | {len(v)} | {sum(v) / len(v):.6g}")
     return "\n".join(out)
@@ -157,11 +169,16 @@ if __name__ == "__main__":
     ap.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
     ap.add_argument("--json", default=None)
     ap.add_argument("--command", default="")
+    ap.add_argument("--where", default=None, help="pmc: COUNTER>=VALUE keeps the dispatches that reach it")
     a = ap.parse_args()
     if a.mode == "stats":
         print(kernel_stats(a.dirs[0]))
     elif a.mode == "pmc":
-        print(pmc(a.dirs[0]))
+        where = None
+        if a.where:
+            c, v = a.where.split(">=")
+            where = (c.strip(), float(v))
+        print(pmc(a.dirs[0], where))
     else:
         t = traffic(a.dirs[0], a.dirs[1], a.kernel, a.copy_bytes)
         t["command"] = a.command

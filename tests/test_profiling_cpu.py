@@ -15,3 +15,16 @@ def test_hash_ignores_comments_and_layout_but_not_code():
     assert kernel_source_hash(files.get) == base
     files["step.hip"] = "int f() { return 2; }"
     assert kernel_source_hash(files.get) != base
+
+
+def test_pmc_filter_keeps_only_dispatches_that_reach_the_minimum(tmp_path):
+    from paper_0912_3824_amd.profiling import pmc
+    rows = ["Dispatch_Id,Kernel_Name,Grid_Size,Counter_Name,Counter_Value"]
+    for did, (waves, valu) in enumerate([(10, 5.0), (5000, 100.0), (6000, 300.0)]):
+        rows += [f"{did},k_build,64,SQ_WAVES,{waves}", f"{did},k_build,64,SQ_INSTS_VALU,{valu}"]
+    (tmp_path / "run_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    every = pmc(str(tmp_path)).splitlines()
+    busy = pmc(str(tmp_path), ("SQ_WAVES", 1000)).splitlines()
+    assert "k_build | 64 | SQ_INSTS_VALU | 3 | 135" in every
+    assert "k_build | 64 | SQ_INSTS_VALU | 2 | 200" in busy
+    assert "k_build | 64 | SQ_WAVES | 2 | 5500" in busy

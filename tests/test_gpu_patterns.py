@@ -318,6 +318,13 @@ def test_error_paths():
         pool.attach_system(0, s)   # slot busy
     pool.detach(0)
     pool.attach_system(1, s)
+    # launch shapes out of range are refused and leave the shape unchanged
+    before = pool.get_launch()
+    for bad in (dict(build_bulk=-1), dict(build_lanes=3), dict(build_split=257), dict(step_block=96)):
+        with pytest.raises(mdx.MdError) as ei:
+            pool.set_launch(**bad)
+        assert ei.value.status == -1, bad
+        assert pool.get_launch() == before, bad
     pool.step(10)
     assert pool.observables()[1]["step"] == 10
     pool.close()

@@ -85,12 +85,13 @@ __device__ __forceinline__ bool slot_selected(int s, int force_slot, const int *
 // host-forced rebuild visits those of the selected slots (items_pref holds
 // the host's per-slot item counts as a prefix).  `which` names the item
 // count of a listed slot: 3 the sort's, 4 the list build's, 5 the bulk list
-// build's.  `unit` is this worker's index among `nunits` workers; visit(slot, item) is called for each item
-// assigned to it.  Consecutive slots start on different workers so that
-// small replicas spread over the grid.  The slots and their item counts are
-// read 64 at a time, one per lane (a few round trips to memory however many
-// replicas rebuild), then walked from registers; visit is called from one
-// place only, so that its code is emitted once.
+// build's.  `unit` is this worker's index among `nunits` workers;
+// visit(slot, item) is called for each item assigned to it.  Consecutive
+// slots start on different workers so that small replicas spread over the
+// grid.  The slots and their item counts are read 64 at a time, one per lane
+// (a few round trips to memory however many replicas rebuild), then walked
+// from registers; visit is called from one place only, so that its code is
+// emitted once.
 template <class F>
 __device__ __forceinline__ void for_items(const int *rlist, const int *items_pref, const RepDev *rep,
                                           int max_slots, int force_slot, const Ctl *ctl, int which,

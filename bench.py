@@ -248,6 +248,62 @@ def cpu_baseline(n: int, temperature: float):
                                         f"({one['extra_builds']} rebuilds), {one['per_step_s']:.3f} s per step"}}
 
 
+_CPU_CFG_CHILD = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import md_inputs as I
+from oracle import oracle as O
+O.build(force=False)
+cfg, route, steps = sys.argv[2], sys.argv[3], int(sys.argv[4])
+make = {"lj4000": lambda: I.make_lj(4000, seed=20240101),
+        "ka64k": lambda: I.make_ka(64_000, 0.7, seed=20240101),
+        "ka1m": lambda: I.make_ka(1_000_000, 0.5, seed=20240101)}[cfg]
+s = make()
+if route == "cells":
+    t0 = time.perf_counter()
+    builds = O.vv_lists(s.pos, s.vel, s.box, s.species, s.table, s.dt, steps, s.skin)[4]
+    sec, work, note = time.perf_counter() - t0, s.n * steps, f"{builds} list builds included"
+elif route == "brute":
+    t0 = time.perf_counter()
+    O.vv(s.pos, s.vel, s.box, s.species, s.table, s.dt, steps)
+    sec, work, note = time.perf_counter() - t0, s.n * steps, "all N^2 pairs every step"
+else:
+    m = steps
+    sel = np.arange(m, dtype=np.int32) * (s.n // m)
+    t0 = time.perf_counter()
+    O.forces(s.pos, s.box, s.species, s.table, sel)
+    sec = (time.perf_counter() - t0) * s.n / m
+    work, note = s.n, f"forces of {m} evenly spaced particles against all N, scaled to all N (one step)"
+print(json.dumps({"n": s.n, "seconds": sec, "rate": work / sec, "note": note}))
+"""
+
+
+def cpu_configs():
+    """The oracle on the three single-system configurations, on all host
+    cores: the cell-list / Verlet-list route (LJ 4000: 1000 steps; KA 64k:
+    1000 steps; KA 1M: 10 steps, list builds included) and brute force (LJ
+    4000: 200 steps; KA 64k: 1 step; KA 1M: one step's forces from a sample
+    of 2048 particles against all N, scaled).  A baseline beside the GPU
+    figures, bounded to about a minute in all."""
+    import subprocess
+    cores = len(os.sched_getaffinity(0))
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    plan = [("lj4000", "cells", 1000), ("lj4000", "brute", 200), ("ka64k", "cells", 1000),
+            ("ka64k", "brute", 1), ("ka1m", "cells", 10), ("ka1m", "sample", 2048)]
+    out = {"unit": "particle-steps/s", "cores": threads, "kind": "oracle", "runs": []}
+    for cfg, route, steps in plan:
+        r = subprocess.run([sys.executable, "-c", _CPU_CFG_CHILD, ROOT, cfg, route, str(steps)],
+                           env=env, capture_output=True, text=True, check=True)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+        out["runs"].append({"config": cfg, "route": "brute" if route == "sample" else route,
+                            "steps": 1 if route == "sample" else steps, "n": d["n"],
+                            "value": d["rate"], "seconds": round(d["seconds"], 3), "sample": d["note"]})
+        log(f"cpu {cfg} {route}: {d['rate']:.4g} particle-steps/s ({d['note']})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +325,8 @@ def main():
     ap.add_argument("--drift-replicas", type=int, default=8, help="independent replicas of the drift measurement")
     ap.add_argument("--no-patterns", action="store_true",
                     help="skip the batched (256 replicas) and served (40 jobs) pattern measurements")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on LJ 4000, KA 64k and KA 1M (cell lists and brute force)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -389,6 +447,8 @@ def main():
         big = systems[0] if len(systems) == 1 else max(systems, key=lambda q: q.n)
         cpu = cpu_baseline(big.n, big.temperature)
         log(f"cpu baseline: {cpu}")
+        if args.cpu_configs:
+            cpu["configs"] = cpu_configs()
 
     out = {
         "metric": "particle-steps/s (Kob-Andersen mixture, whole MD step)",

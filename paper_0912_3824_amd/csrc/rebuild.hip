@@ -215,8 +215,14 @@ __device__ __forceinline__ bool in_cell(const PermArgs &a, const RepDev &rp, int
     return fixed_cell(X.x, X.y, X.z, rp.nd) == c;
 }
 
+// The sort waits on chains of memory round trips rather than on issue, so in
+// double-single and FP64 it is compiled for 6 waves per SIMD (at most 80
+// VGPRs, no spills) instead of the 4 its unconstrained register use allows;
+// its grid takes one full residency at that occupancy.  The FP32 and
+// MIXED64 forms would spill at 80 VGPRs and keep their own allocation.
 template <int P>
-__global__ void __launch_bounds__(256) k_permute(const PermArgs a)
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((P == PREC_DS || P == PREC_FP64) ? 6 : 1))) k_permute(const PermArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
